@@ -1,0 +1,211 @@
+/*
+ * tn_sketch.h -- C ABI of the MI355X (gfx950) sketching estimators for full
+ * tensor network contraction, after "Approximating Tensor Network Contraction
+ * with Sketches" (arXiv 2603.07387).
+ *
+ * A network is the paper's tc(X_1 x ... x X_p, E) (Def. 1-3):
+ *   - tensor k has order q_k and owns the consecutive global modes
+ *     off_k .. off_k + q_k - 1 (off_0 = 0, off_{k+1} = off_k + q_k);
+ *   - dims[u] is the size n_u of global mode u;
+ *   - edges[2e], edges[2e+1] are the 0-based global modes (u, v) of
+ *     contraction e, with u != v and n_u = n_v (Def. 1).  The paper counts
+ *     modes from 1;
+ *   - data[k] points to tensor k in DEVICE memory, row-major (vec() is
+ *     lexicographic order, Preliminaries).
+ * Every mode must take part in exactly one contraction: the estimators cover
+ * full TNC (Theorem 1), under WLOG 1 of the Methods section.
+ *
+ * Estimators:
+ *   TN_CYCLIC  -- the first method, for any network (Eq. (1), Algorithm 1):
+ *                 edge e draws a count sketch C_u for its first mode u and
+ *                 gives its complement C'_u (Def. 14) to the second mode v.
+ *   TN_ACYCLIC -- the second method, for acyclic networks (Eq. (2),
+ *                 Algorithms 2-5): recursive sketches built leaves-to-root.
+ *
+ * Hash family (Def. 10-11 ask for 2-wise independent buckets and 4-wise
+ * independent signs; the paper fixes no construction).  Over P = 2^31 - 1,
+ * with mix() the SplitMix64 output function (Steele, Lea, Flood 2014):
+ *   key  = mix(mix(mix(seed_j) ^ sample) ^ stream),  raw_i = mix(key ^ i) >> 33
+ *   h(i) = ((a1 i + a0) mod P) mod m,  a0 = raw_0 mod P, a1 = 1 + raw_1 mod (P-1)
+ *   s(i) = +1 if (c3 i^3 + c2 i^2 + c1 i + c0) mod P is even else -1,
+ *          c_i = raw_{2+i} mod P
+ * seed_j = seed + j for network j of a plan.  Streams: edge e -> e; the
+ * acyclic method's tensor-sketch count sketches T_{l,j} of tensor k, side d
+ * -> 2^62 + k 2^32 + l 2^16 + 2j + d (domain [m]); padding sketches of
+ * tensor k, slot j -> 2^63 + k 2^32 + j (domain [1]).
+ *
+ * Packed hash entry (int32): bits 0..30 bucket h, bit 31 set when s = -1.
+ *
+ * Errors: every entry point returns TN_OK (0) or a negative code; the text of
+ * the last error on the calling thread is returned by tn_last_error().
+ * Nothing throws across this boundary.  Validation runs on the host before any
+ * device work, so argument errors never leave work queued.
+ *
+ * Streams: `stream` arguments are hipStream_t values (NULL = default stream).
+ * Device work is queued asynchronously on that stream unless stated.
+ */
+#ifndef TN_SKETCH_H
+#define TN_SKETCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define TN_OK 0
+#define TN_ERR_ARG (-1)         /* malformed argument (null, negative size, bad enum) */
+#define TN_ERR_DIMS (-2)        /* contracted modes of different size (n_u != n_v) */
+#define TN_ERR_HYPEREDGE (-3)   /* a mode in more than one contraction (WLOG 1) */
+#define TN_ERR_SELFLOOP (-4)    /* acyclic method: a contraction inside one tensor */
+#define TN_ERR_CYCLIC (-5)      /* acyclic method on a cyclic or disconnected network */
+#define TN_ERR_PARTIAL (-6)     /* a free (uncontracted) mode: partial TNC is not supported */
+#define TN_ERR_OOM (-7)         /* device or host allocation failed */
+#define TN_ERR_HIP (-8)         /* a HIP runtime call failed */
+#define TN_ERR_UNSUPPORTED (-9) /* a size outside the library's limits (see each call) */
+
+/* Element types of tensor data. */
+#define TN_F64 0
+#define TN_F32 1
+#define TN_BF16 2
+
+/* Estimators. */
+#define TN_CYCLIC 1
+#define TN_ACYCLIC 2
+
+/* Plan flags. */
+#define TN_FLAG_GRAPH 0x1u      /* capture each estimate's launches in a hipGraph and replay it */
+#define TN_FLAG_PROFILE 0x2u    /* record HIP events around every kernel launch (not with GRAPH) */
+
+/* Kernel kinds for tn_plan_kernel_time. */
+#define TN_KERNEL_HASH 0        /* count-sketch table generation */
+#define TN_KERNEL_SKETCH 1      /* sketching pass: cyclic scatter / acyclic leaf+SMVP sweep */
+#define TN_KERNEL_COMBINE 2     /* cyclic: DFT + product + sum; acyclic: tensor-sketch combine */
+#define TN_KERNEL_STATS 3       /* per-network sample mean / variance */
+
+typedef struct tn_network {
+  int32_t p;                 /* number of tensors, >= 1 */
+  const int32_t *order;      /* host, p entries: q_k >= 1 */
+  const int64_t *dims;       /* host, sum_k q_k entries: n_u >= 1 */
+  const void *const *data;   /* host array of p DEVICE pointers (row-major tensors) */
+  int32_t dtype;             /* TN_F64 | TN_F32 | TN_BF16; all tensors alike */
+  int32_t t;                 /* number of contractions |E| */
+  const int32_t *edges;      /* host, 2t global 0-based mode ids */
+} tn_network;
+
+typedef struct tn_plan tn_plan;
+
+/*
+ * tn_sketch_plan -- validate a batch of networks and prepare an estimator.
+ *   nets, n_nets : structures (orders, dims, edges, dtype; data may be NULL
+ *                  here, it is bound by each tn_sketch_estimate call).
+ *   method       : TN_CYCLIC (any network) or TN_ACYCLIC (trees only).
+ *   m            : sketch size (the paper's m), a power of two,
+ *                  1 <= m <= 16384 for TN_CYCLIC, 2 <= m <= 65536 for TN_ACYCLIC.
+ *   samples      : S >= 1 independent sketch samples per network; sample r
+ *                  uses hash key (seed + j, r, stream) for network j.
+ *   root         : TN_ACYCLIC root tensor o (Algorithm 2), same for every
+ *                  network; -1 lets the planner pick tensor 0.  Ignored for
+ *                  TN_CYCLIC.
+ *   flags        : TN_FLAG_* bits.
+ *   out          : receives the plan; the library owns it and its device
+ *                  memory until tn_plan_destroy.
+ * Errors: TN_ERR_ARG, TN_ERR_DIMS, TN_ERR_HYPEREDGE, TN_ERR_SELFLOOP,
+ * TN_ERR_CYCLIC, TN_ERR_PARTIAL, TN_ERR_UNSUPPORTED (mode size > 2^20,
+ * order > 16, m outside the limits), TN_ERR_OOM, TN_ERR_HIP.
+ * Uses the current HIP device; the plan is bound to it.
+ */
+int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64_t m,
+                   int64_t samples, uint64_t seed, int32_t root, uint32_t flags,
+                   tn_plan **out);
+
+/*
+ * tn_sketch_estimate -- run every sample of every network of the plan.
+ *   nets      : the plan's networks again (same structure, same order); only
+ *               their data pointers are read.  Buffers must stay valid until
+ *               the queued work completes.
+ *   stream    : hipStream_t for all device work.
+ *   stats     : DEVICE, 2 * n_nets doubles: per network the sample mean of the
+ *               S estimates (the averaged estimate) and their unbiased sample
+ *               variance (0 when S = 1).  FP64.
+ *   samples_out : DEVICE, n_nets * S doubles (network-major), each sample's
+ *               estimate; may be NULL.
+ * Work is asynchronous on `stream`; the call does not synchronize.  Calls on
+ * one plan must not overlap (the plan's workspace is reused).
+ */
+int tn_sketch_estimate(tn_plan *plan, const tn_network *nets, void *stream, double *stats,
+                       double *samples_out);
+
+/*
+ * tn_contract_exact -- exact full contraction of one network in FP64 on the
+ * device (pairwise contractions in a greedy order; Def. 1-3).  Any network
+ * whose every mode is contracted; self-contractions (traces) are allowed.
+ *   out : HOST pointer to one double.  The call synchronizes `stream`.
+ * Errors: TN_ERR_ARG, TN_ERR_DIMS, TN_ERR_HYPEREDGE, TN_ERR_PARTIAL,
+ * TN_ERR_UNSUPPORTED (an intermediate over 2^31 entries), TN_ERR_OOM, TN_ERR_HIP.
+ */
+int tn_contract_exact(const tn_network *net, void *stream, double *out);
+
+/* Release a plan and its device memory (synchronizes the device first). NULL is ignored. */
+void tn_plan_destroy(tn_plan *plan);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *tn_last_error(void);
+
+/*
+ * tn_plan_query -- plan sizes.  key: 0 = hash-table width W (packed entries per
+ * sample), 1 = number of hash streams, 2 = S, 3 = m, 4 = n_nets,
+ * 5 = total tensors, 6 = sketch-vector slots per sample
+ * (one per tensor), 7 = method, 8 = samples sketched per pass over the data,
+ * 9 = samples per launch (workspace chunk).
+ * Returns the value, or a negative code.
+ */
+int64_t tn_plan_query(const tn_plan *plan, int32_t key);
+
+/*
+ * tn_plan_stream -- describe hash stream i (0 <= i < tn_plan_query(plan, 1)):
+ * its network index, stream id (as in the hash family above), domain size n
+ * and offset of its n packed entries within one sample's table.
+ */
+int tn_plan_stream(const tn_plan *plan, int64_t i, int32_t *net, uint64_t *stream_id,
+                   int64_t *n, int64_t *offset);
+
+/*
+ * tn_plan_get_hashes -- write the packed hash tables of samples
+ * [first, first + count) to `out` (DEVICE, count * W int32, sample-major), as
+ * the estimator uses them (drawn from the family, or the injected tables).
+ */
+int tn_plan_get_hashes(tn_plan *plan, int64_t first, int64_t count, void *stream, int32_t *out);
+
+/*
+ * tn_plan_set_hashes -- test hook: replace the hash family by explicit tables
+ * for every sample (DEVICE, S * W packed int32, sample-major; copied on
+ * `stream`).  Passing NULL returns the plan to the hash family.
+ */
+int tn_plan_set_hashes(tn_plan *plan, const int32_t *tables, void *stream);
+
+/*
+ * tn_plan_get_sketches -- test hook: the time-domain sketch vectors of samples
+ * [first, first + count), as FP64 into `out` (DEVICE, count * slots * m
+ * doubles, sample-major, slots as in tn_plan_query key 6).  TN_CYCLIC: y_k =
+ * T_k vec(X_k) for every tensor (Algorithm 1's x_k before the DFT).
+ * TN_ACYCLIC: x_l = C_{k,l} mat(X_l) R_l^T r_l for each non-root tensor l and
+ * x_o = R_o vec(X_o) in the root's slot (Algorithm 2).
+ */
+int tn_plan_get_sketches(tn_plan *plan, const tn_network *nets, int64_t first, int64_t count,
+                         void *stream, double *out);
+
+/*
+ * tn_plan_kernel_time -- with TN_FLAG_PROFILE: total device time in ms and the
+ * number of launches of one kernel kind (TN_KERNEL_*) recorded since the
+ * previous call for that kind.  The events are recorded on the stream each
+ * kernel was launched on; the call waits for them.
+ */
+int tn_plan_kernel_time(tn_plan *plan, int32_t kind, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TN_SKETCH_H */

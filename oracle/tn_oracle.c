@@ -192,7 +192,9 @@ int orc_tc_full(int p, const int *order, const int64_t *dims, const double *cons
   for (int u = 0; u < q; ++u) if (edge_of[u] < 0) { free(edge_of); return -3; }
   int64_t *edims = malloc((size_t)(t > 0 ? t : 1) * sizeof(int64_t));
   int64_t *eidx = calloc((size_t)(t > 0 ? t : 1), sizeof(int64_t));
-  for (int e = 0; e < t; ++e) edims[e] = dims[edges[2 * e]];
+  double terms = 1.0;
+  for (int e = 0; e < t; ++e) { edims[e] = dims[edges[2 * e]]; terms *= (double)edims[e]; }
+  if (terms > 17179869184.0) { free(edge_of); free(edims); free(eidx); return -7; }  /* > 2^34 */
   double acc = 0.0;
   do {
     double prod = 1.0;

@@ -1,0 +1,267 @@
+"""ctypes binding of libtnsketch.so: argument marshalling only.
+
+Functions carry the C names of include/tn_sketch.h.  Tensors are torch tensors
+on the current HIP device; streams default to torch's current stream.  Every
+non-zero return code raises TNError with the library's message.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loaded first: the library then shares torch's HIP runtime
+
+TN_OK = 0
+TN_ERR_ARG = -1
+TN_ERR_DIMS = -2
+TN_ERR_HYPEREDGE = -3
+TN_ERR_SELFLOOP = -4
+TN_ERR_CYCLIC = -5
+TN_ERR_PARTIAL = -6
+TN_ERR_OOM = -7
+TN_ERR_HIP = -8
+TN_ERR_UNSUPPORTED = -9
+TN_F64, TN_F32, TN_BF16 = 0, 1, 2
+TN_CYCLIC, TN_ACYCLIC = 1, 2
+TN_FLAG_GRAPH = 0x1
+TN_FLAG_PROFILE = 0x2
+TN_KERNEL_HASH, TN_KERNEL_SKETCH, TN_KERNEL_COMBINE, TN_KERNEL_STATS = 0, 1, 2, 3
+
+_DTYPES = {torch.float64: TN_F64, torch.float32: TN_F32, torch.bfloat16: TN_BF16}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libtnsketch.so")
+_lib = None
+
+
+class TNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class tn_network(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int32),
+        ("order", ctypes.POINTER(ctypes.c_int32)),
+        ("dims", ctypes.POINTER(ctypes.c_int64)),
+        ("data", ctypes.POINTER(ctypes.c_void_p)),
+        ("dtype", ctypes.c_int32),
+        ("t", ctypes.c_int32),
+        ("edges", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+def lib_path():
+    return _LIBPATH
+
+
+def load():
+    """Load the built library (no fallback: raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        raise RuntimeError(f"{_LIBPATH} is not built; run `python -m paper_2603_07387_amd.build`")
+    L = ctypes.CDLL(_LIBPATH)
+    P = ctypes.POINTER
+    vp, i32, i64, u64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
+    net_p = P(tn_network)
+    L.tn_sketch_plan.argtypes = [net_p, i32, i32, i64, i64, u64, i32, u32, P(vp)]
+    L.tn_sketch_plan.restype = ctypes.c_int
+    L.tn_sketch_estimate.argtypes = [vp, net_p, vp, vp, vp]
+    L.tn_sketch_estimate.restype = ctypes.c_int
+    L.tn_contract_exact.argtypes = [net_p, vp, P(ctypes.c_double)]
+    L.tn_contract_exact.restype = ctypes.c_int
+    L.tn_plan_destroy.argtypes = [vp]
+    L.tn_plan_destroy.restype = None
+    L.tn_last_error.argtypes = []
+    L.tn_last_error.restype = ctypes.c_char_p
+    L.tn_plan_query.argtypes = [vp, i32]
+    L.tn_plan_query.restype = ctypes.c_int64
+    L.tn_plan_stream.argtypes = [vp, i64, P(i32), P(u64), P(i64), P(i64)]
+    L.tn_plan_stream.restype = ctypes.c_int
+    L.tn_plan_get_hashes.argtypes = [vp, i64, i64, vp, vp]
+    L.tn_plan_get_hashes.restype = ctypes.c_int
+    L.tn_plan_set_hashes.argtypes = [vp, vp, vp]
+    L.tn_plan_set_hashes.restype = ctypes.c_int
+    L.tn_plan_get_sketches.argtypes = [vp, net_p, i64, i64, vp, vp]
+    L.tn_plan_get_sketches.restype = ctypes.c_int
+    L.tn_plan_kernel_time.argtypes = [vp, i32, P(ctypes.c_double), P(i64)]
+    L.tn_plan_kernel_time.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def tn_last_error():
+    return load().tn_last_error().decode(errors="replace")
+
+
+def _check(rc):
+    if rc < 0:
+        raise TNError(int(rc), tn_last_error())
+    return rc
+
+
+def _stream(stream):
+    if stream is None:
+        if not torch.cuda.is_initialized():
+            return ctypes.c_void_p(0)      # default stream; nothing queued by torch yet
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class NetworkSpec:
+    """A tn_network: structure from (orders, dims, edges) and device tensors."""
+
+    def __init__(self, orders, dims, edges, tensors=None, dtype=None):
+        self.orders = list(orders)
+        self.dims = list(dims)
+        self.edges = [int(m) for e in edges for m in e]
+        self.p = len(self.orders)
+        self._order = (ctypes.c_int32 * max(1, self.p))(*self.orders)
+        self._dims = (ctypes.c_int64 * max(1, len(self.dims)))(*self.dims)
+        self._edges = (ctypes.c_int32 * max(1, len(self.edges)))(*self.edges)
+        self._data = (ctypes.c_void_p * max(1, self.p))()
+        self.tensors = None
+        if dtype is None:
+            dtype = tensors[0].dtype if tensors else torch.float32
+        self.dtype = _DTYPES[dtype]
+        if tensors is not None:
+            self.bind(tensors)
+
+    @classmethod
+    def from_network(cls, net, tensors=None, dtype=None):
+        return cls(net.orders, net.dims, net.edges, tensors, dtype)
+
+    def bind(self, tensors):
+        if len(tensors) != self.p:
+            raise ValueError("one tensor per network tensor is required")
+        for t in tensors:
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous (row-major)")
+            if _DTYPES[t.dtype] != self.dtype:
+                raise ValueError("all tensors must share the network dtype")
+        self.tensors = list(tensors)
+        for k, t in enumerate(tensors):
+            self._data[k] = t.data_ptr()
+        return self
+
+    def struct(self):
+        return tn_network(self.p, self._order, self._dims, self._data, self.dtype,
+                          len(self.edges) // 2, self._edges)
+
+
+def _array(specs):
+    arr = (tn_network * len(specs))(*[s.struct() for s in specs])
+    return arr
+
+
+def tn_sketch_plan(specs, method, m, samples, seed, root=-1, flags=0):
+    handle = ctypes.c_void_p()
+    _check(load().tn_sketch_plan(_array(specs), len(specs), method, m, samples, seed, root, flags,
+                                 ctypes.byref(handle)))
+    return handle
+
+
+def tn_sketch_estimate(plan, specs, stream, stats, samples_out=None):
+    return _check(load().tn_sketch_estimate(plan, _array(specs), _stream(stream), _ptr(stats),
+                                            _ptr(samples_out)))
+
+
+def tn_contract_exact(spec, stream=None):
+    out = ctypes.c_double(0.0)
+    _check(load().tn_contract_exact(_array([spec]), _stream(stream), ctypes.byref(out)))
+    return out.value
+
+
+def tn_plan_destroy(plan):
+    load().tn_plan_destroy(plan)
+
+
+def tn_plan_query(plan, key):
+    return int(_check(load().tn_plan_query(plan, key)))
+
+
+def tn_plan_stream(plan, i):
+    net, sid, n, off = ctypes.c_int32(), ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().tn_plan_stream(plan, i, ctypes.byref(net), ctypes.byref(sid), ctypes.byref(n),
+                                 ctypes.byref(off)))
+    return net.value, sid.value, n.value, off.value
+
+
+def tn_plan_get_hashes(plan, first, count, stream, out):
+    return _check(load().tn_plan_get_hashes(plan, first, count, _stream(stream), _ptr(out)))
+
+
+def tn_plan_set_hashes(plan, tables, stream=None):
+    return _check(load().tn_plan_set_hashes(plan, _ptr(tables), _stream(stream)))
+
+
+def tn_plan_get_sketches(plan, specs, first, count, stream, out):
+    return _check(load().tn_plan_get_sketches(plan, _array(specs), first, count, _stream(stream),
+                                              _ptr(out)))
+
+
+def tn_plan_kernel_time(plan, kind):
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    _check(load().tn_plan_kernel_time(plan, kind, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+class Plan:
+    """Owns a tn_plan handle; thin methods over the C calls."""
+
+    def __init__(self, specs, method, m, samples, seed, root=-1, flags=0):
+        self.specs = list(specs)
+        self.handle = tn_sketch_plan(self.specs, method, m, samples, seed, root, flags)
+        self.n_nets = len(self.specs)
+        self.S = samples
+        self.m = m
+
+    def query(self, key):
+        return tn_plan_query(self.handle, key)
+
+    def estimate(self, stats=None, samples_out=None, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if stats is None:
+            stats = torch.empty(2 * self.n_nets, dtype=torch.float64, device=dev)
+        tn_sketch_estimate(self.handle, self.specs, stream, stats, samples_out)
+        return stats
+
+    def hashes(self, first=0, count=None, stream=None):
+        count = self.S - first if count is None else count
+        W = self.query(0)
+        out = torch.empty(count * W, dtype=torch.int32, device="cuda")
+        tn_plan_get_hashes(self.handle, first, count, stream, out)
+        return out.view(count, W)
+
+    def set_hashes(self, tables, stream=None):
+        tn_plan_set_hashes(self.handle, tables, stream)
+
+    def sketches(self, first=0, count=1, stream=None):
+        slots = self.query(6)
+        out = torch.empty(count * slots * self.m, dtype=torch.float64, device="cuda")
+        tn_plan_get_sketches(self.handle, self.specs, first, count, stream, out)
+        return out.view(count, slots, self.m)
+
+    def kernel_time(self, kind):
+        return tn_plan_kernel_time(self.handle, kind)
+
+    def streams(self):
+        return [tn_plan_stream(self.handle, i) for i in range(self.query(1))]
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            tn_plan_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

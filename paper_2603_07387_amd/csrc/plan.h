@@ -1,0 +1,122 @@
+// Host-side plan of the tn_sketch library (not part of the public ABI).
+#pragma once
+
+#include <vector>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+constexpr int kMaxOrder = 16;
+constexpr int64_t kMaxDim = 1 << 20;
+constexpr int64_t kMaxTensor = (int64_t)1 << 31;
+
+// Result of validating one network.
+struct NetCheck {
+  int32_t q = 0;
+  std::vector<int32_t> offsets;    // p + 1
+  std::vector<int64_t> sizes;      // entries per tensor
+  std::vector<int32_t> edge_of;    // per mode
+  std::vector<int32_t> tensor_of;  // per mode
+};
+
+int validate_network(const tn_network *n, int index, NetCheck *chk);
+int validate_tree(const tn_network *n, int index, const NetCheck &chk);
+const char *last_error();
+
+struct M2Plan;  // acyclic method, defined in m2.hip
+
+}  // namespace tn
+
+struct tn_plan {
+  int device = 0;
+  int method = 0;
+  int64_t m = 0;
+  int log2m = 0;
+  int64_t S = 0;
+  uint64_t seed = 0;
+  uint32_t flags = 0;
+  int root = 0;
+  int dtype = 0;
+  int n_nets = 0;
+  int64_t n_tensors = 0;
+  size_t max_lds = 65536;
+
+  // structure, for checking the networks passed to estimate()
+  std::vector<int32_t> net_p;
+  std::vector<int64_t> net_tensor0;  // first global tensor of each network
+  std::vector<int64_t> tensor_size;  // entries per global tensor
+  std::vector<std::vector<int32_t>> net_orders;
+
+  // hash streams
+  std::vector<tn::StreamDesc> h_streams;
+  int64_t W = 0;
+  tn::StreamDesc *d_streams = nullptr;
+  int32_t *d_tables = nullptr;    // [chunk][W]
+  int32_t *d_injected = nullptr;  // [S][W] when tables are injected
+
+  // data binding
+  std::vector<const void *> bound;  // last pointers copied to d_data
+  const void **d_data = nullptr;
+
+  // cyclic method
+  std::vector<tn::ModeDesc> h_modes;
+  std::vector<tn::ScatterSlot> h_slots;
+  std::vector<int32_t> h_tslot;  // per global tensor: first slot; n_tensors + 1 entries
+  std::vector<tn::NetDesc> h_nets;
+  tn::ModeDesc *d_modes = nullptr;
+  tn::ScatterSlot *d_slots = nullptr;
+  int32_t *d_tslot = nullptr;
+  tn::NetDesc *d_nets = nullptr;
+  void *d_tw = nullptr;
+  void *d_ybuf = nullptr;
+  int sb = 1;
+  size_t scatter_lds = 0;
+  int64_t chunk = 0;  // samples per workspace pass
+
+  // per-sample estimates [n_nets][S]
+  double *d_est = nullptr;
+
+  // acyclic method
+  tn::M2Plan *m2 = nullptr;
+
+  // profiling events: (kind, start, stop) pending, and a pool of free events
+  struct ProfRec {
+    int kind;
+    hipEvent_t start, stop;
+  };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+
+  // graph replay
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+  double *graph_stats = nullptr;
+  double *graph_samples = nullptr;
+};
+
+namespace tn {
+
+int plan_build(tn_plan *p, const tn_network *nets, int n_nets, int method, int64_t m,
+               int64_t S, uint64_t seed, int root, uint32_t flags);
+int plan_estimate(tn_plan *p, const tn_network *nets, hipStream_t st, double *stats,
+                  double *samples_out);
+void plan_release(tn_plan *p);
+int64_t plan_query(const tn_plan *p, int key);
+int plan_get_hashes(tn_plan *p, int64_t first, int64_t count, hipStream_t st, int32_t *out);
+int plan_set_hashes(tn_plan *p, const int32_t *tables, hipStream_t st);
+int plan_get_sketches(tn_plan *p, const tn_network *nets, int64_t first, int64_t count,
+                      hipStream_t st, double *out);
+int plan_bind(tn_plan *p, const tn_network *nets, hipStream_t st);
+int prof_begin(tn_plan *p, hipStream_t st, hipEvent_t *ev);
+int prof_end(tn_plan *p, hipStream_t st, int kind, hipEvent_t start);
+int plan_kernel_time(tn_plan *p, int kind, double *ms, int64_t *launches);
+
+// acyclic method (m2.hip)
+int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &chk);
+int m2_estimate(tn_plan *p, hipStream_t st, double *est);
+int m2_get_sketches(tn_plan *p, int64_t first, int64_t count, hipStream_t st, double *out);
+void m2_release(tn_plan *p);
+
+}  // namespace tn

@@ -1,0 +1,500 @@
+// Planner and launch sequencing for the estimators.
+//
+// Cyclic method (Eq. (1), Algorithm 1): one hash stream per contraction e of
+// network j (key seed + j, stream e).  The first mode of the contraction owns
+// the count sketch, the second reads its complement (Def. 14).  Each tensor is
+// viewed as a (rows x L) matrix whose L columns cover its trailing modes, and
+// is cut into slots of at most kMaxSlotEntries entries; every slot is streamed
+// once per batch of `sb` samples by the scatter kernel.
+#include <algorithm>
+#include <cstring>
+
+#include "plan.h"
+
+namespace tn {
+namespace {
+
+constexpr int kMaxRowsPerSlot = 2048;
+constexpr size_t kWorkspaceBudget = (size_t)1 << 30;  // tables + sketches per pass
+
+template <typename T>
+int dev_alloc(T **ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return TN_OK;
+  hipError_t e = hipMalloc((void **)ptr, count * sizeof(T));
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return set_error(e == hipErrorOutOfMemory ? TN_ERR_OOM : TN_ERR_HIP,
+                     "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+  }
+  return TN_OK;
+}
+
+template <typename T>
+int upload(T **ptr, const std::vector<T> &v) {
+  int rc = dev_alloc(ptr, v.size());
+  if (rc != TN_OK || v.empty()) return rc;
+  TN_HIP_CHECK(hipMemcpy(*ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return TN_OK;
+}
+
+size_t acc_size(int dtype) { return dtype == TN_F64 ? sizeof(double) : sizeof(float); }
+
+int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &chk) {
+  const size_t as = acc_size(p->dtype);
+  if (p->log2m > kMaxLog2M1)
+    return set_error(TN_ERR_UNSUPPORTED, "cyclic method: m = %lld exceeds %d", (long long)p->m,
+                     1 << kMaxLog2M1);
+  if ((size_t)p->m * 2 * as > p->max_lds)
+    return set_error(TN_ERR_UNSUPPORTED, "cyclic method: the m-point FFT needs %zu bytes of LDS",
+                     (size_t)p->m * 2 * as);
+  int64_t gmode = 0, gtensor = 0;
+  for (int j = 0; j < p->n_nets; ++j) {
+    const tn_network &n = nets[j];
+    const NetCheck &c = chk[(size_t)j];
+    std::vector<int64_t> stream_off((size_t)n.t);
+    for (int e = 0; e < n.t; ++e) {
+      StreamDesc sd{};
+      sd.seed = p->seed + (uint64_t)j;
+      sd.stream = (uint64_t)e;
+      sd.offset = p->W;
+      sd.n = (int32_t)n.dims[n.edges[2 * e]];
+      sd.net = j;
+      stream_off[(size_t)e] = p->W;
+      p->W += sd.n;
+      p->h_streams.push_back(sd);
+    }
+    NetDesc nd{(int32_t)gtensor, (int32_t)(gtensor + n.p)};
+    p->h_nets.push_back(nd);
+    for (int u = 0; u < c.q; ++u) {
+      const int e = c.edge_of[(size_t)u];
+      ModeDesc md{};
+      md.table_off = stream_off[(size_t)e];
+      md.n = (int32_t)n.dims[u];
+      md.comp = (n.edges[2 * e + 1] == u) ? 1 : 0;
+      p->h_modes.push_back(md);
+    }
+    for (int k = 0; k < n.p; ++k, ++gtensor) {
+      const int q = n.order[k];
+      const int32_t mode0 = (int32_t)(gmode + c.offsets[(size_t)k]);
+      int split = q;
+      int64_t L = 1;
+      while (split > 0 && L * n.dims[c.offsets[(size_t)k] + split - 1] <= kMaxCols) {
+        L *= n.dims[c.offsets[(size_t)k] + split - 1];
+        --split;
+      }
+      if (split == q)
+        return set_error(TN_ERR_UNSUPPORTED,
+                         "cyclic method: network %d tensor %d has a last mode of size %lld > %d", j,
+                         k, (long long)n.dims[c.offsets[(size_t)k] + q - 1], kMaxCols);
+      const int64_t R = c.sizes[(size_t)k] / L;
+      const int64_t rows_per = std::max<int64_t>(1, std::min<int64_t>(kMaxRowsPerSlot, kMaxSlotEntries / L));
+      p->h_tslot.push_back((int32_t)p->h_slots.size());
+      for (int64_t r0 = 0; r0 < R; r0 += rows_per) {
+        ScatterSlot sl{};
+        sl.tensor = (int32_t)gtensor;
+        sl.q = q;
+        sl.split = split;
+        sl.L = (int32_t)L;
+        sl.mode0 = mode0;
+        sl.rows = (int32_t)std::min<int64_t>(rows_per, R - r0);
+        sl.row0 = r0;
+        sl.magic = L > 1 ? (uint32_t)(((uint64_t)1 << 32) / (uint64_t)L + 1) : 0u;
+        p->h_slots.push_back(sl);
+      }
+    }
+    gmode += c.q;
+  }
+  p->h_tslot.push_back((int32_t)p->h_slots.size());
+
+  // Samples per scatter block: as many as fit 64 KB of LDS (two blocks per CU),
+  // else one.
+  size_t worst_cols_rows = 0;
+  for (const ScatterSlot &sl : p->h_slots)
+    worst_cols_rows = std::max(worst_cols_rows, (size_t)(sl.L + sl.rows));
+  auto lds_for = [&](int sb) { return (size_t)sb * ((size_t)p->m * as + 4 * worst_cols_rows); };
+  p->sb = 1;
+  for (int sb : {8, 4, 2}) {
+    if (sb <= p->S && lds_for(sb) <= 65536) { p->sb = sb; break; }
+  }
+  p->scatter_lds = lds_for(p->sb);
+  if (p->scatter_lds > p->max_lds)
+    return set_error(TN_ERR_UNSUPPORTED, "cyclic method: scatter needs %zu bytes of LDS", p->scatter_lds);
+
+  const size_t per_sample = (size_t)p->W * 4 + p->h_slots.size() * (size_t)p->m * as;
+  int64_t chunk = (int64_t)std::max<size_t>(1, kWorkspaceBudget / std::max<size_t>(1, per_sample));
+  chunk = std::min<int64_t>(chunk, p->S);
+  chunk = std::min<int64_t>(chunk, 65535);
+  if (chunk > p->sb) chunk = chunk / p->sb * p->sb;
+  p->chunk = chunk;
+
+  int rc;
+  if ((rc = upload(&p->d_streams, p->h_streams)) != TN_OK) return rc;
+  if ((rc = upload(&p->d_modes, p->h_modes)) != TN_OK) return rc;
+  if ((rc = upload(&p->d_slots, p->h_slots)) != TN_OK) return rc;
+  if ((rc = upload(&p->d_tslot, p->h_tslot)) != TN_OK) return rc;
+  if ((rc = upload(&p->d_nets, p->h_nets)) != TN_OK) return rc;
+  if ((rc = dev_alloc(&p->d_tables, (size_t)chunk * (size_t)p->W)) != TN_OK) return rc;
+  unsigned char *yb = nullptr;
+  if ((rc = dev_alloc(&yb, (size_t)chunk * p->h_slots.size() * (size_t)p->m * as)) != TN_OK) return rc;
+  p->d_ybuf = yb;
+  if (p->m >= 2) {
+    unsigned char *tw = nullptr;
+    if ((rc = dev_alloc(&tw, (size_t)(p->m / 2) * 2 * as)) != TN_OK) return rc;
+    p->d_tw = tw;
+    if ((rc = launch_twiddles(p->m, p->dtype, p->d_tw, 0)) != TN_OK) return rc;
+    TN_HIP_CHECK(hipDeviceSynchronize());
+  }
+  return TN_OK;
+}
+
+int m1_tables(tn_plan *p, int64_t c0, int64_t n, hipStream_t st, const int32_t **tables) {
+  if (p->d_injected) {
+    *tables = p->d_injected + c0 * p->W;
+    return TN_OK;
+  }
+  *tables = p->d_tables;
+  hipEvent_t ev = nullptr;
+  int rc = prof_begin(p, st, &ev);
+  if (rc == TN_OK)
+    rc = launch_hashgen(p->d_streams, (int64_t)p->h_streams.size(), p->W, c0, n, p->m,
+                        p->d_tables, st);
+  if (rc == TN_OK) rc = prof_end(p, st, TN_KERNEL_HASH, ev);
+  return rc;
+}
+
+int m1_run(tn_plan *p, hipStream_t st, double *est) {
+  for (int64_t c0 = 0; c0 < p->S; c0 += p->chunk) {
+    const int64_t n = std::min(p->chunk, p->S - c0);
+    const int32_t *tables = nullptr;
+    int rc = m1_tables(p, c0, n, st, &tables);
+    if (rc != TN_OK) return rc;
+    M1Launch L{};
+    L.slots = p->d_slots;
+    L.n_slots = (int64_t)p->h_slots.size();
+    L.modes = p->d_modes;
+    L.data = p->d_data;
+    L.dtype = p->dtype;
+    L.tables = tables;
+    L.W = p->W;
+    L.samples = n;
+    L.sb = p->sb;
+    L.log2m = p->log2m;
+    L.lds_bytes = p->scatter_lds;
+    L.ybuf = p->d_ybuf;
+    hipEvent_t ev = nullptr;
+    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = launch_m1_scatter(L, st)) != TN_OK) return rc;
+    if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
+    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf,
+                                (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, est,
+                                st)) != TN_OK)
+      return rc;
+    if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
+  }
+  return TN_OK;
+}
+
+int run_all(tn_plan *p, hipStream_t st, double *stats, double *est) {
+  int rc = (p->method == TN_CYCLIC) ? m1_run(p, st, est) : m2_estimate(p, st, est);
+  if (rc != TN_OK) return rc;
+  hipEvent_t ev = nullptr;
+  if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+  if ((rc = launch_sample_stats(est, p->n_nets, p->S, stats, st)) != TN_OK) return rc;
+  return prof_end(p, st, TN_KERNEL_STATS, ev);
+}
+
+}  // namespace
+
+int prof_begin(tn_plan *p, hipStream_t st, hipEvent_t *ev) {
+  *ev = nullptr;
+  if (!(p->flags & TN_FLAG_PROFILE)) return TN_OK;
+  if (p->prof_pool.empty()) {
+    hipEvent_t e;
+    TN_HIP_CHECK(hipEventCreate(&e));
+    p->prof_pool.push_back(e);
+  }
+  *ev = p->prof_pool.back();
+  p->prof_pool.pop_back();
+  TN_HIP_CHECK(hipEventRecord(*ev, st));
+  return TN_OK;
+}
+
+int prof_end(tn_plan *p, hipStream_t st, int kind, hipEvent_t start) {
+  if (!(p->flags & TN_FLAG_PROFILE) || !start) return TN_OK;
+  if (p->prof_pool.empty()) {
+    hipEvent_t e;
+    TN_HIP_CHECK(hipEventCreate(&e));
+    p->prof_pool.push_back(e);
+  }
+  hipEvent_t stop = p->prof_pool.back();
+  p->prof_pool.pop_back();
+  TN_HIP_CHECK(hipEventRecord(stop, st));
+  p->prof_pending.push_back({kind, start, stop});
+  return TN_OK;
+}
+
+int plan_kernel_time(tn_plan *p, int kind, double *ms, int64_t *launches) {
+  *ms = 0.0;
+  *launches = 0;
+  if (!(p->flags & TN_FLAG_PROFILE)) return set_error(TN_ERR_ARG, "plan was built without TN_FLAG_PROFILE");
+  std::vector<tn_plan::ProfRec> keep;
+  for (const auto &r : p->prof_pending) {
+    if (r.kind != kind) {
+      keep.push_back(r);
+      continue;
+    }
+    TN_HIP_CHECK(hipEventSynchronize(r.stop));
+    float t = 0.f;
+    TN_HIP_CHECK(hipEventElapsedTime(&t, r.start, r.stop));
+    *ms += t;
+    *launches += 1;
+    p->prof_pool.push_back(r.start);
+    p->prof_pool.push_back(r.stop);
+  }
+  p->prof_pending.swap(keep);
+  return TN_OK;
+}
+
+int plan_build(tn_plan *p, const tn_network *nets, int n_nets, int method, int64_t m, int64_t S,
+               uint64_t seed, int root, uint32_t flags) {
+  p->method = method;
+  p->m = m;
+  p->log2m = 0;
+  while ((1ll << p->log2m) < m) ++p->log2m;
+  p->S = S;
+  p->seed = seed;
+  p->flags = flags;
+  p->root = root < 0 ? 0 : root;
+  p->n_nets = n_nets;
+  std::vector<NetCheck> chk((size_t)n_nets);
+  for (int j = 0; j < n_nets; ++j) {
+    int rc = validate_network(&nets[j], j, &chk[(size_t)j]);
+    if (rc != TN_OK) return rc;
+    if (j > 0 && nets[j].dtype != nets[0].dtype)
+      return set_error(TN_ERR_ARG, "network %d: every network of a plan must share one dtype", j);
+    if (method == TN_ACYCLIC) {
+      if ((rc = validate_tree(&nets[j], j, chk[(size_t)j])) != TN_OK) return rc;
+      if (p->root >= nets[j].p)
+        return set_error(TN_ERR_ARG, "network %d: root %d outside [0, %d)", j, p->root, nets[j].p);
+    }
+    p->net_p.push_back(nets[j].p);
+    p->net_tensor0.push_back(p->n_tensors);
+    p->net_orders.emplace_back(nets[j].order, nets[j].order + nets[j].p);
+    for (int k = 0; k < nets[j].p; ++k) p->tensor_size.push_back(chk[(size_t)j].sizes[(size_t)k]);
+    p->n_tensors += nets[j].p;
+  }
+  p->dtype = nets[0].dtype;
+  if (method == TN_ACYCLIC && (m < 2 || m > 65536))
+    return set_error(TN_ERR_UNSUPPORTED, "acyclic method: m = %lld outside [2, 65536]", (long long)m);
+  if (n_nets > 65535 && method == TN_CYCLIC)
+    return set_error(TN_ERR_UNSUPPORTED, "at most 65535 networks per plan");
+  TN_HIP_CHECK(hipGetDevice(&p->device));
+  int lds = 0;
+  TN_HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
+  p->max_lds = (size_t)lds;
+  int rc = (method == TN_CYCLIC) ? m1_build(p, nets, chk) : m2_build(p, nets, chk);
+  if (rc != TN_OK) {
+    plan_release(p);
+    return rc;
+  }
+  if ((rc = dev_alloc(&p->d_est, (size_t)n_nets * (size_t)S)) != TN_OK) { plan_release(p); return rc; }
+  if ((rc = dev_alloc(&p->d_data, (size_t)p->n_tensors)) != TN_OK) { plan_release(p); return rc; }
+  p->bound.assign((size_t)p->n_tensors, nullptr);
+  TN_HIP_CHECK(hipMemset(p->d_data, 0, (size_t)p->n_tensors * sizeof(void *)));
+  TN_HIP_CHECK(hipDeviceSynchronize());
+  return TN_OK;
+}
+
+int plan_bind(tn_plan *p, const tn_network *nets, hipStream_t st) {
+  bool changed = false;
+  for (int j = 0; j < p->n_nets; ++j) {
+    const tn_network &n = nets[j];
+    if (n.p != p->net_p[(size_t)j] || n.dtype != p->dtype || !n.order || !n.data)
+      return set_error(TN_ERR_ARG, "network %d does not match the plan", j);
+    for (int k = 0; k < n.p; ++k) {
+      if (n.order[k] != p->net_orders[(size_t)j][(size_t)k])
+        return set_error(TN_ERR_ARG, "network %d tensor %d: order differs from the plan", j, k);
+      if (!n.data[k]) return set_error(TN_ERR_ARG, "network %d tensor %d: null data", j, k);
+      const size_t g = (size_t)(p->net_tensor0[(size_t)j] + k);
+      if (p->bound[g] != n.data[k]) {
+        p->bound[g] = n.data[k];
+        changed = true;
+      }
+    }
+  }
+  if (changed) {
+    // Pageable source: the copy is staged before the call returns, so the host
+    // array may change right after.
+    TN_HIP_CHECK(hipMemcpyAsync(p->d_data, p->bound.data(), p->bound.size() * sizeof(void *),
+                                hipMemcpyHostToDevice, st));
+  }
+  return TN_OK;
+}
+
+int plan_estimate(tn_plan *p, const tn_network *nets, hipStream_t st, double *stats,
+                  double *samples_out) {
+  int rc = plan_bind(p, nets, st);
+  if (rc != TN_OK) return rc;
+  double *est = samples_out ? samples_out : p->d_est;
+  if (!(p->flags & TN_FLAG_GRAPH)) return run_all(p, st, stats, est);
+
+  // Graph replay: capture once per (stream, output buffers), then relaunch.
+  if (!p->graph_exec || p->graph_stream != st || p->graph_stats != stats || p->graph_samples != est) {
+    if (p->graph_exec) {
+      (void)hipGraphExecDestroy(p->graph_exec);
+      p->graph_exec = nullptr;
+    }
+    if (p->graph) {
+      (void)hipGraphDestroy(p->graph);
+      p->graph = nullptr;
+    }
+    hipStream_t cap = st;
+    bool own = false;
+    if (cap == nullptr) {
+      TN_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      own = true;
+    }
+    TN_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    rc = run_all(p, cap, stats, est);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(cap, &g);
+    if (own) (void)hipStreamDestroy(cap);
+    if (rc != TN_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ee != hipSuccess) return set_error(TN_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    p->graph = g;
+    TN_HIP_CHECK(hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
+    p->graph_stream = st;
+    p->graph_stats = stats;
+    p->graph_samples = est;
+  }
+  TN_HIP_CHECK(hipGraphLaunch(p->graph_exec, st));
+  return TN_OK;
+}
+
+void plan_release(tn_plan *p) {
+  (void)hipDeviceSynchronize();
+  for (const auto &r : p->prof_pending) {
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+  }
+  for (hipEvent_t e : p->prof_pool) (void)hipEventDestroy(e);
+  p->prof_pending.clear();
+  p->prof_pool.clear();
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->graph_exec = nullptr;
+  p->graph = nullptr;
+  if (p->m2) m2_release(p);
+  void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data, p->d_modes, p->d_slots,
+                  p->d_tslot,   p->d_nets,   p->d_tw,       p->d_ybuf, p->d_est};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  p->d_streams = nullptr;
+  p->d_tables = p->d_injected = nullptr;
+  p->d_data = nullptr;
+  p->d_modes = nullptr;
+  p->d_slots = nullptr;
+  p->d_tslot = nullptr;
+  p->d_nets = nullptr;
+  p->d_tw = p->d_ybuf = nullptr;
+  p->d_est = nullptr;
+}
+
+int64_t plan_query(const tn_plan *p, int key) {
+  switch (key) {
+    case 0: return p->W;
+    case 1: return (int64_t)p->h_streams.size();
+    case 2: return p->S;
+    case 3: return p->m;
+    case 4: return p->n_nets;
+    case 5: return p->n_tensors;
+    case 6: return p->n_tensors;
+    case 7: return p->method;
+    case 8: return p->sb;
+    case 9: return p->chunk;
+    default: return set_error(TN_ERR_ARG, "unknown query key %d", key);
+  }
+}
+
+int plan_get_hashes(tn_plan *p, int64_t first, int64_t count, hipStream_t st, int32_t *out) {
+  if (first < 0 || count < 0 || first + count > p->S)
+    return set_error(TN_ERR_ARG, "samples [%lld, %lld) outside [0, %lld)", (long long)first,
+                     (long long)(first + count), (long long)p->S);
+  if (p->d_injected) {
+    TN_HIP_CHECK(hipMemcpyAsync(out, p->d_injected + first * p->W,
+                                (size_t)count * (size_t)p->W * sizeof(int32_t),
+                                hipMemcpyDeviceToDevice, st));
+    return TN_OK;
+  }
+  for (int64_t c = 0; c < count; c += 65535) {
+    const int64_t n = std::min<int64_t>(65535, count - c);
+    int rc = launch_hashgen(p->d_streams, (int64_t)p->h_streams.size(), p->W, first + c, n, p->m,
+                            out + c * p->W, st);
+    if (rc != TN_OK) return rc;
+  }
+  return TN_OK;
+}
+
+int plan_set_hashes(tn_plan *p, const int32_t *tables, hipStream_t st) {
+  if (p->graph_exec) {
+    (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = nullptr;
+    (void)hipGraphDestroy(p->graph);
+    p->graph = nullptr;
+  }
+  if (!tables) {
+    if (p->d_injected) {
+      TN_HIP_CHECK(hipStreamSynchronize(st));
+      TN_HIP_CHECK(hipFree(p->d_injected));
+    }
+    p->d_injected = nullptr;
+    return TN_OK;
+  }
+  if (!p->d_injected) {
+    int rc = dev_alloc(&p->d_injected, (size_t)p->S * (size_t)p->W);
+    if (rc != TN_OK) return rc;
+  }
+  return launch_copy_i32(tables, p->d_injected, p->S * p->W, st);
+}
+
+int plan_get_sketches(tn_plan *p, const tn_network *nets, int64_t first, int64_t count,
+                      hipStream_t st, double *out) {
+  if (first < 0 || count < 0 || first + count > p->S)
+    return set_error(TN_ERR_ARG, "samples [%lld, %lld) outside [0, %lld)", (long long)first,
+                     (long long)(first + count), (long long)p->S);
+  int rc = plan_bind(p, nets, st);
+  if (rc != TN_OK) return rc;
+  if (p->method == TN_ACYCLIC) return m2_get_sketches(p, first, count, st, out);
+  for (int64_t c0 = first; c0 < first + count; c0 += p->chunk) {
+    const int64_t n = std::min(p->chunk, first + count - c0);
+    const int32_t *tables = nullptr;
+    if ((rc = m1_tables(p, c0, n, st, &tables)) != TN_OK) return rc;
+    M1Launch L{};
+    L.slots = p->d_slots;
+    L.n_slots = (int64_t)p->h_slots.size();
+    L.modes = p->d_modes;
+    L.data = p->d_data;
+    L.dtype = p->dtype;
+    L.tables = tables;
+    L.W = p->W;
+    L.samples = n;
+    L.sb = p->sb;
+    L.log2m = p->log2m;
+    L.lds_bytes = p->scatter_lds;
+    L.ybuf = p->d_ybuf;
+    if ((rc = launch_m1_scatter(L, st)) != TN_OK) return rc;
+    if ((rc = launch_m1_slots_to_tensors(p->d_tslot, p->n_tensors, p->dtype, p->d_ybuf,
+                                         (int64_t)p->h_slots.size(), n, p->log2m,
+                                         out + (c0 - first) * p->n_tensors * p->m, st)) != TN_OK)
+      return rc;
+  }
+  return TN_OK;
+}
+
+}  // namespace tn

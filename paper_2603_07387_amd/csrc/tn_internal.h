@@ -1,0 +1,120 @@
+// Internal definitions of the tn_sketch library: device-visible descriptors,
+// kernel launchers and error helpers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/tn_sketch.h"
+
+namespace tn {
+
+// ---------------------------------------------------------------------------
+// Error reporting (thread-local text behind tn_last_error()).
+// ---------------------------------------------------------------------------
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+
+#define TN_HIP_CHECK(call)                                                        \
+  do {                                                                            \
+    hipError_t _e = (call);                                                       \
+    if (_e != hipSuccess)                                                         \
+      return ::tn::set_error(TN_ERR_HIP, "%s failed: %s (%s:%d)", #call,          \
+                             hipGetErrorString(_e), __FILE__, __LINE__);          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Hash family (see tn_sketch.h): one descriptor per stream.
+// ---------------------------------------------------------------------------
+struct StreamDesc {
+  uint64_t seed;     // network seed (plan seed + network index)
+  uint64_t stream;   // stream id
+  int64_t offset;    // first packed entry of this stream in a sample's table
+  int32_t n;         // domain size
+  int32_t net;       // owning network
+};
+
+// Packed hash entry: bucket in bits 0..30, bit 31 set for sign -1.
+constexpr uint32_t kSignBit = 0x80000000u;
+
+// ---------------------------------------------------------------------------
+// Cyclic method (Eq. (1)).
+// ---------------------------------------------------------------------------
+// Per global mode: where its count sketch lives and whether it is the
+// complement side of its contraction (Def. 14).
+struct ModeDesc {
+  int64_t table_off;  // offset of the edge's stream in a sample's table
+  int32_t n;          // mode size
+  int32_t comp;       // 1: second mode of the edge -> bucket (m - h) mod m
+};
+
+// One scatter work item: a block of rows of one tensor.  The tensor is viewed
+// as a matrix: row index over modes [0, split), column index over modes
+// [split, q) with L columns.
+struct ScatterSlot {
+  int32_t tensor;     // global tensor index (into the data pointer array)
+  int32_t q;          // order
+  int32_t split;      // first column mode
+  int32_t L;          // number of columns
+  int32_t mode0;      // global mode id of the tensor's first mode
+  int32_t rows;       // rows in this block
+  int64_t row0;       // first row of the block
+  uint32_t magic;     // ceil(2^32 / L): row = umulhi(e, magic) for e < 2^21
+  int32_t pad;
+};
+
+// Per network: its tensors [t0, t1) and, per tensor, slots
+// [slot_begin[k], slot_begin[k+1]).
+struct NetDesc {
+  int32_t t0, t1;
+};
+
+// Limits of the cyclic scatter.
+constexpr int kMaxCols = 4096;          // columns per slot (packed tables in LDS)
+constexpr int kMaxSlotEntries = 1 << 16;  // entries per scatter block
+constexpr int kMaxLog2M1 = 14;          // m <= 16384 (complex FFT in LDS)
+
+struct M1Launch {
+  const ScatterSlot *slots;
+  int64_t n_slots;
+  const ModeDesc *modes;
+  const void *const *data;   // per global tensor
+  int dtype;
+  const int32_t *tables;     // [samples][W]
+  int64_t W;
+  int64_t samples;           // samples in this chunk
+  int sb;                    // samples per scatter block
+  int log2m;
+  size_t lds_bytes;
+  void *ybuf;                // [samples][n_slots][m] (double for F64, float otherwise)
+};
+
+int launch_hashgen(const StreamDesc *streams, int64_t n_streams, int64_t W, int64_t sample0,
+                   int64_t samples, int64_t m, int32_t *out, hipStream_t st);
+
+int launch_m1_scatter(const M1Launch &L, hipStream_t st);
+
+int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tensor_slot_begin,
+                      int dtype, const void *ybuf, int64_t n_slots, int64_t samples,
+                      int64_t sample0, int64_t S, int log2m, const void *twiddles,
+                      double *est, hipStream_t st);
+
+int launch_m1_slots_to_tensors(const int32_t *tensor_slot_begin, int64_t n_tensors, int dtype,
+                               const void *ybuf, int64_t n_slots, int64_t samples, int log2m,
+                               double *out, hipStream_t st);
+
+int launch_twiddles(int64_t m, int dtype, void *out, hipStream_t st);
+
+int launch_sample_stats(const double *est, int64_t n_nets, int64_t S, double *stats,
+                        hipStream_t st);
+
+int launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Exact contraction.
+// ---------------------------------------------------------------------------
+int contract_exact(const tn_network *net, hipStream_t st, double *out);
+
+}  // namespace tn

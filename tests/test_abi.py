@@ -1,0 +1,89 @@
+"""Host-only checks of the C ABI: the library loads, exports every declared
+symbol, and validates networks (error codes) before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import tn_workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(tn_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_2603_07387_amd as T
+    T.load()
+    return T
+
+
+def test_exports_every_declared_symbol(T):
+    names = _declared()
+    assert "tn_sketch_plan" in names and "tn_sketch_estimate" in names and "tn_contract_exact" in names
+    lib = ctypes.CDLL(T.lib_path())
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def _spec(T, net, dtype="float32"):
+    import torch
+    return T.NetworkSpec.from_network(net, dtype=getattr(torch, dtype))
+
+
+@pytest.mark.parametrize("net,method,code", [
+    (W.Network([2, 2], [3, 3, 4, 3], [(0, 2), (1, 3)]), 1, -2),            # n_u != n_v
+    (W.Network([2, 1], [3, 3, 3], [(0, 2), (1, 2)]), 1, -3),               # mode 2 twice
+    (W.Network([2, 2], [3, 3, 3, 3], [(0, 2)]), 1, -6),                    # free modes
+    (W.Network([2, 1], [3, 3, 3], [(0, 0)]), 1, -1),                       # u == v
+    (W.Network([2, 2], [3, 3, 3, 3], [(0, 2), (1, 3)]), 2, -5),            # double bond: cycle
+    (W.Network([2], [3, 3], [(0, 1)]), 2, -4),                             # trace: self-loop
+])
+def test_validation_codes(T, net, method, code):
+    with pytest.raises(T.TNError) as ei:
+        T.tn_sketch_plan([_spec(T, net)], method, 16, 4, 0)
+    assert ei.value.code == code
+    assert T.tn_last_error()
+
+
+def test_argument_codes(T):
+    net = W.triangle(4)
+    s = _spec(T, net, "float64")
+    for m in (0, 3, 100):
+        with pytest.raises(T.TNError) as ei:
+            T.tn_sketch_plan([s], 1, m, 4, 0)
+        assert ei.value.code == T.TN_ERR_ARG
+    with pytest.raises(T.TNError) as ei:
+        T.tn_sketch_plan([s], 1, 16, 0, 0)
+    assert ei.value.code == T.TN_ERR_ARG
+    with pytest.raises(T.TNError) as ei:
+        T.tn_sketch_plan([s], 3, 16, 4, 0)
+    assert ei.value.code == T.TN_ERR_ARG
+    with pytest.raises(T.TNError) as ei:
+        T.tn_sketch_plan([s], 1, 16, 4, 0, flags=0x80)
+    assert ei.value.code == T.TN_ERR_ARG
+    big = W.Network([1, 1], [1 << 21, 1 << 21], [(0, 1)])
+    with pytest.raises(T.TNError) as ei:
+        T.tn_sketch_plan([_spec(T, big)], 1, 16, 4, 0)
+    assert ei.value.code == T.TN_ERR_UNSUPPORTED
+    # a second network of another dtype
+    with pytest.raises(T.TNError) as ei:
+        T.tn_sketch_plan([s, _spec(T, net, "float32")], 1, 16, 4, 0)
+    assert ei.value.code == T.TN_ERR_ARG
+
+
+def test_exact_validation(T):
+    with pytest.raises(T.TNError) as ei:
+        T.tn_contract_exact(_spec(T, W.Network([2, 2], [3, 3, 3, 3], [(0, 2)])))
+    assert ei.value.code == T.TN_ERR_PARTIAL
