@@ -77,6 +77,10 @@ extern "C" {
 /* Plan flags. */
 #define TN_FLAG_GRAPH 0x1u      /* capture each estimate's launches in a hipGraph and replay it */
 #define TN_FLAG_PROFILE 0x2u    /* record HIP events around every kernel launch (not with GRAPH) */
+#define TN_FLAG_AUTOTUNE 0x4u   /* first estimate times the sketching pass at each feasible
+                                   samples-per-pass value on the bound data and keeps the
+                                   fastest (that call synchronizes its stream); cached per
+                                   plan shape for the life of the process */
 
 /* Kernel kinds for tn_plan_kernel_time. */
 #define TN_KERNEL_HASH 0        /* count-sketch table generation */

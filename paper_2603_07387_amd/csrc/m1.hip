@@ -9,7 +9,8 @@
 // Kernels:
 //   m1_scatter  : one block streams one slot (a run of rows of one tensor)
 //                 once from HBM, coalesced, and accumulates the sketches of SB
-//                 samples in LDS (packed bucket/sign tables in LDS too).
+//                 samples in LDS in 64-bit fixed point (packed bucket/sign
+//                 tables in LDS too).
 //   m1_combine  : one block per (network, sample): two real sketches share one
 //                 complex FFT in LDS (z = y_a + i y_b), the pair's product
 //                 spectrum Y_a Y_b = (Z[j]^2 - conj(Z[-j])^2) / 4i is folded into
@@ -33,26 +34,61 @@ __device__ __forceinline__ float to_acc<uint16_t>(uint16_t v) {
   return __uint_as_float(((uint32_t)v) << 16);
 }
 
-template <typename T, typename A>
-__device__ __forceinline__ A load_entry(const T *p, int64_t i) {
-  return (A)to_acc<T>(p[i]);
+__device__ __forceinline__ double to_acc_any(double v) { return v; }
+__device__ __forceinline__ float to_acc_any(float v) { return v; }
+__device__ __forceinline__ float to_acc_any(uint16_t v) { return to_acc<uint16_t>(v); }
+
+// 16-byte vector of tensor entries (clang vector types, so they can be read
+// through a global-address-space pointer: global_load_dwordx4, not flat).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = f32x4;
+};
+template <>
+struct Vec16<double> {
+  using type = f64x2;
+};
+template <>
+struct Vec16<uint16_t> {
+  using type = u16x8;
+};
+
+// N consecutive packed column hashes from LDS (16-byte aligned for N >= 4,
+// 8-byte aligned for N = 2).
+template <int N>
+__device__ __forceinline__ void load_cols(const uint32_t *p, uint32_t *out);
+template <>
+__device__ __forceinline__ void load_cols<2>(const uint32_t *p, uint32_t *out) {
+  const uint2 t = *reinterpret_cast<const uint2 *>(p);
+  out[0] = t.x; out[1] = t.y;
 }
 template <>
-__device__ __forceinline__ double load_entry<double, double>(const double *p, int64_t i) {
-  return p[i];
+__device__ __forceinline__ void load_cols<4>(const uint32_t *p, uint32_t *out) {
+  const uint4 t = *reinterpret_cast<const uint4 *>(p);
+  out[0] = t.x; out[1] = t.y; out[2] = t.z; out[3] = t.w;
+}
+template <>
+__device__ __forceinline__ void load_cols<8>(const uint32_t *p, uint32_t *out) {
+  load_cols<4>(p, out);
+  load_cols<4>(p + 4, out + 4);
 }
 
 // Packed bucket/sign of a contiguous run of modes for one index: the sum of
 // the modes' buckets mod m and the product of their signs.
 __device__ __forceinline__ uint32_t combine_modes(const int32_t *__restrict__ tab,
                                                   const ModeDesc *__restrict__ modes,
-                                                  int u_first, int u_last, int64_t idx,
+                                                  int u_first, int u_last, uint32_t idx,
                                                   uint32_t m, uint32_t mask) {
   uint32_t acc = 0;
   for (int u = u_last; u >= u_first; --u) {
     const ModeDesc md = modes[u];
-    const int64_t d = idx % md.n;
-    idx /= md.n;
+    const uint32_t d = idx % (uint32_t)md.n;
+    idx /= (uint32_t)md.n;
     const uint32_t v = (uint32_t)tab[md.table_off + d];
     uint32_t h = v & ~kSignBit;
     if (md.comp) h = (m - h) & mask;
@@ -61,12 +97,20 @@ __device__ __forceinline__ uint32_t combine_modes(const int32_t *__restrict__ ta
   return acc;
 }
 
+// The sketches of one block are accumulated in 64-bit fixed point in LDS:
+// x -> round(x 2^scale) with ds_add_u64, which on gfx950 sustains about 16x the
+// rate of LDS float atomics, and makes every sketch independent of the order
+// of the atomic adds.  The block scale follows a running maximum of |x|:
+// scale = 62 - ceil(log2 N) - e with max|x| < 2^e, so N terms of the slot
+// cannot overflow; when a larger |x| appears the accumulators are shifted
+// right to the new scale before any further add.
 template <typename T, typename A, int SB>
 __global__ __launch_bounds__(256) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
     int64_t samples, int log2m, int64_t n_slots, A *__restrict__ ybuf) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ unsigned long long s_max[2];
   const ScatterSlot sl = slots[blockIdx.x];
   const int tid = threadIdx.x;
   const int64_t s0 = (int64_t)blockIdx.y * SB;
@@ -74,11 +118,12 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
   const uint32_t m = 1u << log2m, mask = m - 1;
   const int L = sl.L, rows = sl.rows;
 
-  A *ysk = reinterpret_cast<A *>(smem);                         // [SB][m]
-  uint32_t *colt = reinterpret_cast<uint32_t *>(ysk + SB * m);  // [SB][L]
-  uint32_t *rowt = colt + SB * L;                               // [SB][rows]
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);  // [SB][m]
+  uint32_t *colt = reinterpret_cast<uint32_t *>(smem + ((SB * m * 8 + 15) & ~15u));  // [SB][L]
+  uint32_t *rowt = colt + SB * L;                                         // [SB][rows]
 
-  for (int i = tid; i < SB * (int)m; i += 256) ysk[i] = (A)0;
+  for (int i = tid; i < SB * (int)m; i += 256) acc[i] = 0ull;
+  if (tid < 2) s_max[tid] = 0ull;
   for (int i = tid; i < nsb * L; i += 256) {
     const int s = i / L, c = i - s * L;
     colt[s * L + c] = combine_modes(tables + (s0 + s) * W, modes, sl.mode0 + sl.split,
@@ -87,22 +132,138 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
   for (int i = tid; i < nsb * rows; i += 256) {
     const int s = i / rows, r = i - s * rows;
     rowt[s * rows + r] = combine_modes(tables + (s0 + s) * W, modes, sl.mode0,
-                                       sl.mode0 + sl.split - 1, sl.row0 + r, m, mask);
+                                       sl.mode0 + sl.split - 1, (uint32_t)(sl.row0 + r), m, mask);
   }
   __syncthreads();
 
   const T *X = reinterpret_cast<const T *>(data[sl.tensor]) + sl.row0 * (int64_t)L;
   const uint32_t N = (uint32_t)rows * (uint32_t)L;
-  for (uint32_t e = tid; e < N; e += 256) {
-    const A x = load_entry<T, A>(X, e);
-    const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
-    const uint32_t c = e - r * (uint32_t)L;
+  // Headroom: N terms below 2^(62 - lgN) each cannot overflow, and every
+  // scaled term stays below 2^51 so the magic-number conversion is exact.
+  const int lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
+  int scale = 0;       // accumulators hold x 2^scale
+  double sc = 1.0;     // 2^scale
+  double bound = 0.0;  // every |x| seen is < bound (0: none seen yet)
+  int par = 0;
+
+  // Block-wide running max of |x| (double-buffered so the read of one
+  // iteration cannot race with the next iteration's update), then a rescale
+  // when it reaches the bound.  Called by every thread once per iteration.
+  auto update_scale = [&](double lmax) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
+    if ((tid & 63) == 0) atomicMax(&s_max[par], (unsigned long long)__double_as_longlong(lmax));
+    __syncthreads();
+    const double bm = __longlong_as_double((long long)s_max[par]);
+    par ^= 1;
+    if (bm >= bound && bm > 0.0) {
+      int e;
+      (void)frexp(bm, &e);  // bm < 2^e
+      const int ns = 62 - lgN - e;
+      if (bound > 0.0 && scale > ns) {
+        const int d = scale - ns;
+        for (int i = tid; i < SB * (int)m; i += 256)
+          acc[i] = (unsigned long long)((long long)acc[i] >> d);
+        __syncthreads();
+      }
+      scale = ns;
+      sc = ldexp(1.0, ns);
+      bound = ldexp(1.0, e);
+    }
+  };
+  // round(x 2^scale) for |x 2^scale| < 2^51: adding 1.5 2^52 leaves the
+  // rounded integer in the low mantissa bits.
+  auto to_fixed = [&](double x) -> long long {
+    const double kMagic = 6755399441055744.0;
+    return __double_as_longlong(fma(x, sc, kMagic)) - __double_as_longlong(kMagic);
+  };
+  // Add entry x (row r, column c) to the sketch of every sample of the batch.
+  auto scatter_one = [&](double x, uint32_t r, uint32_t c) {
+    const long long v = to_fixed(x);
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       if (s < nsb) {
         const uint32_t hv = rowt[s * rows + r], lv = colt[s * L + c];
         const uint32_t b = (hv + lv) & mask;
-        atomicAdd(&ysk[s * m + b], ((hv ^ lv) & kSignBit) ? -x : x);
+        atomicAdd(&acc[s * m + b], (unsigned long long)(((hv ^ lv) & kSignBit) ? -v : v));
+      }
+    }
+  };
+  // VEC consecutive entries of one row: the row's packed hash is read once per
+  // sample and the VEC column hashes with one vector LDS read.
+  auto scatter_vec = [&](const long long *q, uint32_t r, uint32_t c) {
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      if (s < nsb) {
+        const uint32_t hv = rowt[s * rows + r];
+        uint32_t lv[16 / sizeof(T)];
+        load_cols<16 / sizeof(T)>(colt + s * L + c, lv);
+#pragma unroll
+        for (int i = 0; i < (int)(16 / sizeof(T)); ++i) {
+          const uint32_t b = (hv + lv[i]) & mask;
+          atomicAdd(&acc[s * m + b],
+                    (unsigned long long)(((hv ^ lv[i]) & kSignBit) ? -q[i] : q[i]));
+        }
+      }
+    }
+  };
+  constexpr int VEC = 16 / (int)sizeof(T);   // entries per 16-byte load
+  constexpr int UNROLL = 4;                  // 16-byte loads in flight per thread
+  const bool vec = (L % VEC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  if (vec) {
+    // Rows are multiples of VEC long and the slot starts 16-byte aligned, so
+    // the VEC entries of one load share a row.
+    using V = typename Vec16<T>::type;
+    const V __attribute__((address_space(1))) *Xv =
+        (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X);
+    const uint32_t NV = N / VEC;
+    for (uint32_t v0 = 0; v0 < NV; v0 += 256 * UNROLL) {
+      // Unconditional loads (index clamped into the slot) keep all UNROLL loads
+      // in flight; out-of-range lanes are masked when the values are used.
+      V buf[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) buf[u] = Xv[min(v0 + u * 256 + tid, NV - 1)];
+      double lmax = 0.0;
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const T *xs = reinterpret_cast<const T *>(&buf[u]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+      }
+      update_scale(lmax);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const uint32_t v = v0 + u * 256 + tid;
+        if (v < NV) {
+          const uint32_t e = v * VEC;
+          const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
+          const uint32_t c = e - r * (uint32_t)L;
+          const T *xs = reinterpret_cast<const T *>(&buf[u]);
+          long long q[VEC];
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) q[i] = to_fixed((double)to_acc_any(xs[i]));
+          scatter_vec(q, r, c);
+        }
+      }
+    }
+  } else {
+    const T __attribute__((address_space(1))) *Xg =
+        (const T __attribute__((address_space(1))) *)X;
+    for (uint32_t e0 = 0; e0 < N; e0 += 256 * UNROLL) {
+      T buf[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) buf[u] = Xg[min(e0 + u * 256 + tid, N - 1)];
+      double lmax = 0.0;
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) lmax = fmax(lmax, fabs((double)to_acc_any(buf[u])));
+      update_scale(lmax);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const uint32_t e = e0 + u * 256 + tid;
+        if (e < N) {
+          const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
+          scatter_one((double)to_acc_any(buf[u]), r, e - r * (uint32_t)L);
+        }
       }
     }
   }
@@ -111,7 +272,8 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
   for (int i = tid; i < nsb * (int)m; i += 256) {
     const int s = i >> log2m;
     const int b = i & mask;
-    ybuf[((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + b] = ysk[i];
+    ybuf[((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + b] =
+        (A)ldexp((double)(long long)acc[i], -scale);
   }
 }
 

@@ -72,7 +72,10 @@ struct tn_plan {
   void *d_ybuf = nullptr;
   int sb = 1;
   size_t scatter_lds = 0;
-  int64_t chunk = 0;  // samples per workspace pass
+  int64_t chunk = 0;        // samples per workspace pass
+  int64_t chunk_alloc = 0;  // samples the workspace was sized for
+  size_t worst_cols_rows = 0;
+  bool tuned = false;
 
   // per-sample estimates [n_nets][S]
   double *d_est = nullptr;

@@ -8,6 +8,7 @@
 // once per batch of `sb` samples by the scatter kernel.
 #include <algorithm>
 #include <cstring>
+#include <cstdlib>
 
 #include "plan.h"
 
@@ -113,12 +114,20 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   size_t worst_cols_rows = 0;
   for (const ScatterSlot &sl : p->h_slots)
     worst_cols_rows = std::max(worst_cols_rows, (size_t)(sl.L + sl.rows));
-  auto lds_for = [&](int sb) { return (size_t)sb * ((size_t)p->m * as + 4 * worst_cols_rows); };
+  // 64-bit fixed-point accumulators (8 bytes per bucket) plus packed tables.
+  // (+64: the accumulator block is padded to 16 bytes and the kernel keeps a
+  // 16-byte running maximum in static LDS.)
+  auto lds_for = [&](int sb) { return (size_t)sb * ((size_t)p->m * 8 + 4 * worst_cols_rows) + 64; };
   p->sb = 1;
   for (int sb : {8, 4, 2}) {
-    if (sb <= p->S && lds_for(sb) <= 65536) { p->sb = sb; break; }
+    if (sb <= p->S && lds_for(sb) <= 81920) { p->sb = sb; break; }
+  }
+  if (const char *env = getenv("TN_SCATTER_SB")) {
+    const int sb = atoi(env);
+    if ((sb == 1 || sb == 2 || sb == 4 || sb == 8 || sb == 16) && lds_for(sb) <= p->max_lds) p->sb = sb;
   }
   p->scatter_lds = lds_for(p->sb);
+  p->worst_cols_rows = worst_cols_rows;
   if (p->scatter_lds > p->max_lds)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: scatter needs %zu bytes of LDS", p->scatter_lds);
 
@@ -126,7 +135,8 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   int64_t chunk = (int64_t)std::max<size_t>(1, kWorkspaceBudget / std::max<size_t>(1, per_sample));
   chunk = std::min<int64_t>(chunk, p->S);
   chunk = std::min<int64_t>(chunk, 65535);
-  if (chunk > p->sb) chunk = chunk / p->sb * p->sb;
+  p->chunk_alloc = chunk;
+  if (chunk > 16) chunk = chunk / 16 * 16;  // a multiple of every samples-per-pass choice
   p->chunk = chunk;
 
   int rc;
@@ -194,6 +204,74 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
       return rc;
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
   }
+  return TN_OK;
+}
+
+// Autotuner of the sketching pass: samples per pass trades one HBM read of the
+// tensors per pass against LDS size (hence blocks per CU).  Each feasible value
+// is timed on the plan's first workspace chunk with the bound data.
+struct TuneKey {
+  int64_t slots, entries_hint, m, S, W;
+  int dtype;
+  bool operator==(const TuneKey &o) const {
+    return slots == o.slots && entries_hint == o.entries_hint && m == o.m && S == o.S && W == o.W &&
+           dtype == o.dtype;
+  }
+};
+static std::vector<std::pair<TuneKey, int>> g_tuned;
+
+int m1_autotune(tn_plan *p, hipStream_t st) {
+  int64_t entries = 0;
+  for (const ScatterSlot &sl : p->h_slots) entries += (int64_t)sl.rows * sl.L;
+  const TuneKey key{(int64_t)p->h_slots.size(), entries, p->m, p->S, p->W, p->dtype};
+  auto apply = [&](int sb) {
+    p->sb = sb;
+    p->scatter_lds = (size_t)sb * ((size_t)p->m * 8 + 4 * p->worst_cols_rows) + 64;
+  };
+  for (const auto &kv : g_tuned)
+    if (kv.first == key) { apply(kv.second); return TN_OK; }
+  const int64_t n = std::min(p->chunk, p->S);
+  const int32_t *tables = nullptr;
+  int rc = m1_tables(p, 0, n, st, &tables);
+  if (rc != TN_OK) return rc;
+  hipEvent_t e0, e1;
+  TN_HIP_CHECK(hipEventCreate(&e0));
+  TN_HIP_CHECK(hipEventCreate(&e1));
+  int best = p->sb;
+  float best_ms = 1e30f;
+  for (int sb : {1, 2, 4, 8, 16}) {
+    if (sb > 1 && sb > n) break;
+    const size_t lds = (size_t)sb * ((size_t)p->m * 8 + 4 * p->worst_cols_rows) + 64;
+    if (lds > p->max_lds) break;
+    M1Launch L{};
+    L.slots = p->d_slots;
+    L.n_slots = (int64_t)p->h_slots.size();
+    L.modes = p->d_modes;
+    L.data = p->d_data;
+    L.dtype = p->dtype;
+    L.tables = tables;
+    L.W = p->W;
+    L.samples = n;
+    L.sb = sb;
+    L.log2m = p->log2m;
+    L.lds_bytes = lds;
+    L.ybuf = p->d_ybuf;
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && rc == TN_OK; ++rep) {
+      if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
+      if (rc == TN_OK) rc = launch_m1_scatter(L, st);
+      if (rc == TN_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
+      if (rc == TN_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: sync");
+      if (rc == TN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (rc != TN_OK) break;
+    if (ms < best_ms) { best_ms = ms; best = sb; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != TN_OK) return rc;
+  apply(best);
+  g_tuned.push_back({key, best});
   return TN_OK;
 }
 
@@ -338,6 +416,10 @@ int plan_estimate(tn_plan *p, const tn_network *nets, hipStream_t st, double *st
                   double *samples_out) {
   int rc = plan_bind(p, nets, st);
   if (rc != TN_OK) return rc;
+  if ((p->flags & TN_FLAG_AUTOTUNE) && !p->tuned && p->method == TN_CYCLIC) {
+    if ((rc = m1_autotune(p, st)) != TN_OK) return rc;
+    p->tuned = true;
+  }
   double *est = samples_out ? samples_out : p->d_est;
   if (!(p->flags & TN_FLAG_GRAPH)) return run_all(p, st, stats, est);
 

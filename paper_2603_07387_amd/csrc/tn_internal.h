@@ -72,7 +72,7 @@ struct NetDesc {
 };
 
 // Limits of the cyclic scatter.
-constexpr int kMaxCols = 4096;          // columns per slot (packed tables in LDS)
+constexpr int kMaxCols = 1024;          // columns per slot (packed tables in LDS)
 constexpr int kMaxSlotEntries = 1 << 16;  // entries per scatter block
 constexpr int kMaxLog2M1 = 14;          // m <= 16384 (complex FFT in LDS)
 

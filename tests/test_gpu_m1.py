@@ -212,6 +212,23 @@ def test_graph_replay(T, orc):
         del junk
 
 
+def test_bitwise_deterministic_across_schedules(T, orc):
+    """Fixed-point sketch accumulation: estimates are bit-identical run to run and
+    for every samples-per-pass choice of the autotuner."""
+    nets = [W.torus(L=2, D=16, seed=9), W.random_network(4, 3)]
+    a, views = make_plan(T, nets, "float32", 1024, 24, 8)
+    b, _ = make_plan(T, nets, "float32", 1024, 24, 8, flags=T.TN_FLAG_AUTOTUNE)
+    _, ga = run(a)
+    _, ga2 = run(a)
+    _, gb = run(b)
+    assert np.array_equal(ga, ga2)
+    assert np.array_equal(ga, gb)
+    assert b.query(8) in (1, 2, 4, 8, 16)
+    for j, net in enumerate(views):
+        ref, scale = oracle_samples(orc, net, 1024, 8 + j, range(3))
+        assert np.all(np.abs(ga[j, :3] - ref) <= 1e-5 * scale)
+
+
 def _brute_force_sized(count, limit=5e7):
     """Random cyclic networks whose brute-force oracle sum has <= limit terms."""
     out = []
