@@ -115,7 +115,8 @@ def main():
         ts = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda", td) for x in n.data]
         specs.append(T.NetworkSpec.from_network(n, ts))
     torch.cuda.synchronize()
-    plan = T.Plan(specs, T.TN_CYCLIC, m, S, 0, flags=T.TN_FLAG_PROFILE | T.TN_FLAG_AUTOTUNE)
+    flags = T.TN_FLAG_PROFILE | (0 if os.environ.get("TN_SCATTER_SB") else T.TN_FLAG_AUTOTUNE)
+    plan = T.Plan(specs, T.TN_CYCLIC, m, S, 0, flags=flags)
     stats = torch.empty(2 * len(nets), dtype=torch.float64, device="cuda")
     for _ in range(a.warmup):
         plan.estimate(stats)

@@ -226,12 +226,58 @@ def m2_estimate(net, m, seed, sample, root=0, want_trace=False, tables=None):
     return out
 
 
-def m2_scale(net, m, seed, sample, root=0):
+def m2_streams(net, root=0):
+    """Hash streams Method 2 draws for a tree rooted at `root`: (stream id, domain).
+    Contractions e over [n_e]; per tensor with c >= 1 children, padded order
+    qt = next power of two, the tensor sketches T_{l,j} (two count sketches over
+    [m] each, marked by domain None) and the qt - c padding sketches over [1]."""
+    partner = {}
+    for (u, v) in net.edges:
+        partner[u], partner[v] = v, u
+    parent_mode = {root: None}
+    nchild = {}
+    queue = [root]
+    while queue:
+        k = queue.pop(0)
+        nchild[k] = 0
+        for u in net.modes(k):
+            if u == parent_mode[k]:
+                continue
+            l = net.tensor_of(partner[u])
+            parent_mode[l] = partner[u]
+            nchild[k] += 1
+            queue.append(l)
+    out = [(e, net.dims[u]) for e, (u, _) in enumerate(net.edges)]
+    for k in sorted(nchild):
+        c = nchild[k]
+        if c == 0:
+            continue
+        qt = 1
+        while qt < c:
+            qt *= 2
+        l = qt
+        while l >= 2:
+            for j in range(l // 2):
+                out.append((stream_tsketch(k, l, j, 0), None))
+                out.append((stream_tsketch(k, l, j, 1), None))
+            l //= 2
+        for j in range(c, qt):
+            out.append((stream_pad(k, j), 1))
+    return out
+
+
+def m2_scale(net, m, seed, sample, root=0, want_trace=False):
     """Rounding-error scale for Method 2: the same estimate with every entry
-    replaced by |X| and every sign by +1, which bounds the magnitude of every
-    partial sum the estimator forms."""
+    replaced by |X| and every sign by +1 (same buckets), which bounds the
+    magnitude of every partial sum the estimator forms.  With want_trace, the
+    per-tensor sketch bounds as well."""
     absnet = net.with_data([np.abs(np.asarray(x, dtype=np.float64)) for x in net.data])
-    return abs(m2_estimate(absnet, m, seed, sample, root)["estimate"])
+    tables = {}
+    for sid, n in m2_streams(net, root):
+        h, _ = hash_table(seed, sample, sid, m if n is None else n, m)
+        tables[sid] = (h, np.ones_like(h))
+    out = m2_estimate(absnet, m, seed, sample, root, want_trace=want_trace, tables=tables)
+    return out if want_trace else abs(out["estimate"])
 
 
 def dft(x, inverse=False):

@@ -124,17 +124,24 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
 
   for (int i = tid; i < SB * (int)m; i += 256) acc[i] = 0ull;
   if (tid < 2) s_max[tid] = 0ull;
+  // Packed tables hold the byte offset of the bucket (bucket * 8) and the sign
+  // bit, so a sum of a row and a column entry masked with 8(m - 1) is the LDS
+  // offset of the target accumulator.
+  auto to_offset = [](uint32_t v) { return ((v & ~kSignBit) << 3) | (v & kSignBit); };
   for (int i = tid; i < nsb * L; i += 256) {
     const int s = i / L, c = i - s * L;
-    colt[s * L + c] = combine_modes(tables + (s0 + s) * W, modes, sl.mode0 + sl.split,
-                                    sl.mode0 + sl.q - 1, c, m, mask);
+    colt[s * L + c] = to_offset(combine_modes(tables + (s0 + s) * W, modes, sl.mode0 + sl.split,
+                                              sl.mode0 + sl.q - 1, c, m, mask));
   }
   for (int i = tid; i < nsb * rows; i += 256) {
     const int s = i / rows, r = i - s * rows;
-    rowt[s * rows + r] = combine_modes(tables + (s0 + s) * W, modes, sl.mode0,
-                                       sl.mode0 + sl.split - 1, (uint32_t)(sl.row0 + r), m, mask);
+    rowt[s * rows + r] = to_offset(combine_modes(tables + (s0 + s) * W, modes, sl.mode0,
+                                                 sl.mode0 + sl.split - 1,
+                                                 (uint32_t)(sl.row0 + r), m, mask));
   }
   __syncthreads();
+  const uint32_t mask8 = mask << 3;
+  char *acc8 = reinterpret_cast<char *>(smem);
 
   const T *X = reinterpret_cast<const T *>(data[sl.tensor]) + sl.row0 * (int64_t)L;
   const uint32_t N = (uint32_t)rows * (uint32_t)L;
@@ -177,37 +184,33 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
     const double kMagic = 6755399441055744.0;
     return __double_as_longlong(fma(x, sc, kMagic)) - __double_as_longlong(kMagic);
   };
+  // One fixed-point add: the sample's accumulator block starts at s * 8m bytes
+  // and the masked offset sum stays inside it.
+  auto add_fixed = [&](int s, uint32_t hv, uint32_t lv, long long v) {
+    const uint32_t a = ((hv + lv) & mask8) | ((uint32_t)s * (m << 3));
+    atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + a),
+              (unsigned long long)(((hv ^ lv) & kSignBit) ? -v : v));
+  };
   // Add entry x (row r, column c) to the sketch of every sample of the batch.
   auto scatter_one = [&](double x, uint32_t r, uint32_t c) {
     const long long v = to_fixed(x);
+    uint32_t hv[SB], lv[SB];
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      if (s < nsb) {
-        const uint32_t hv = rowt[s * rows + r], lv = colt[s * L + c];
-        const uint32_t b = (hv + lv) & mask;
-        atomicAdd(&acc[s * m + b], (unsigned long long)(((hv ^ lv) & kSignBit) ? -v : v));
-      }
-    }
-  };
-  // VEC consecutive entries of one row: the row's packed hash is read once per
-  // sample and the VEC column hashes with one vector LDS read.
-  auto scatter_vec = [&](const long long *q, uint32_t r, uint32_t c) {
+    for (int s = 0; s < SB; ++s) { hv[s] = rowt[s * rows + r]; lv[s] = colt[s * L + c]; }
 #pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      if (s < nsb) {
-        const uint32_t hv = rowt[s * rows + r];
-        uint32_t lv[16 / sizeof(T)];
-        load_cols<16 / sizeof(T)>(colt + s * L + c, lv);
-#pragma unroll
-        for (int i = 0; i < (int)(16 / sizeof(T)); ++i) {
-          const uint32_t b = (hv + lv[i]) & mask;
-          atomicAdd(&acc[s * m + b],
-                    (unsigned long long)(((hv ^ lv[i]) & kSignBit) ? -q[i] : q[i]));
-        }
-      }
-    }
+    for (int s = 0; s < SB; ++s)
+      if (s < nsb) add_fixed(s, hv[s], lv[s], v);
   };
   constexpr int VEC = 16 / (int)sizeof(T);   // entries per 16-byte load
+  // Row and column entries of every sample for VEC consecutive entries of one
+  // row (all reads issued before any add, so one LDS wait covers them).
+  auto read_tabs = [&](uint32_t r, uint32_t c, uint32_t *hv, uint32_t (*lv)[VEC]) {
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      hv[s] = rowt[s * rows + r];
+      load_cols<VEC>(colt + s * L + c, lv[s]);
+    }
+  };
   constexpr int UNROLL = 4;                  // 16-byte loads in flight per thread
   const bool vec = (L % VEC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
   if (vec) {
@@ -231,18 +234,31 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
         for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
       }
       update_scale(lmax);
+      uint32_t rr[UNROLL], cc[UNROLL];
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
-        const uint32_t v = v0 + u * 256 + tid;
-        if (v < NV) {
-          const uint32_t e = v * VEC;
-          const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
-          const uint32_t c = e - r * (uint32_t)L;
+        const uint32_t e = min(v0 + u * 256 + tid, NV - 1) * VEC;  // clamped: valid table reads
+        rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
+        cc[u] = e - rr[u] * (uint32_t)L;
+      }
+      // Software pipeline: the table reads of vector u + 1 are issued before the
+      // adds of vector u.
+      uint32_t hv[2][SB], lv[2][SB][VEC];
+      read_tabs(rr[0], cc[0], hv[0], lv[0]);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
+        if (v0 + u * 256 + tid < NV) {
           const T *xs = reinterpret_cast<const T *>(&buf[u]);
           long long q[VEC];
 #pragma unroll
           for (int i = 0; i < VEC; ++i) q[i] = to_fixed((double)to_acc_any(xs[i]));
-          scatter_vec(q, r, c);
+#pragma unroll
+          for (int s = 0; s < SB; ++s)
+            if (s < nsb) {
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i]);
+            }
         }
       }
     }
