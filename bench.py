@@ -1,17 +1,23 @@
 """Throughput benchmark of the sketching estimators on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload torus] [--m 1024]
-                    [--samples S] [--batch B] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload torus|batched|ttcat|triangle]
+                    [--m M] [--samples S] [--batch B] [--no-cpu-baseline]
 
 A step is one full pass of the estimator over one batch of synthetic input
 already resident in HBM: hash generation, the sketching pass over every tensor,
-the DFT/product/sum combine and the per-network mean/variance, for every
-sample of every network in the batch.  Prints one JSON line.
+the combine and the per-network mean/variance, for every sample of every
+network in the batch.  Prints one JSON line.
 
-Workloads:
-  torus    4 x 4 periodic lattice of order-4 tensors, bond 16, FP32 U[0,1),
-           cyclic estimator; a batch of B independent tori (B = 256: 1 GiB).
-  triangle three 64 x 64 FP64 N(0,1) matrices, tr(ABC), m = 256.
+Workloads (all inputs seeded and synthetic):
+  torus     4 x 4 periodic lattice of order-4 tensors, bond 16, FP32 U[0,1),
+            cyclic estimator, m = 1024; a batch of B independent tori
+            (B = 256: 1 GiB resident).  Default.
+  batched   4096 random connected cyclic networks, 3-12 tensors, bonds
+            U{2..32}, FP32 N(0,1), cyclic estimator, m = 1024.
+  ttcat     tensor-train caterpillar (32 cores (1,64,64)..(64,64,1) with their
+            physical legs contracted against vectors), FP32 N(0,1/64), acyclic
+            estimator, m = 4096, S = 4096 samples.
+  triangle  three 64 x 64 FP64 N(0,1) matrices, tr(ABC), m = 256.
 """
 from __future__ import annotations
 
@@ -27,6 +33,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
 
 METRIC = "sketch estimates/s at 1e-2 rel. error; % HBM roofline; batched/learned vs plain"
 
@@ -36,67 +43,105 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="torus", choices=["torus", "triangle"])
+    ap.add_argument("--workload", default="torus", choices=["torus", "batched", "ttcat", "triangle"])
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 5 device copies of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
 
 
+def copy_calibration():
+    """Plain 1 GiB device-to-device copies: the reference kernel whose FETCH_SIZE
+    and WRITE_SIZE counters calibrate the HBM traffic of the estimator kernels."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "copies": 5}))
+
+
 def build_workload(a):
-    import numpy as np
     import tn_workloads as W
     if a.workload == "torus":
-        m = a.m or 1024
-        B = a.batch or 256
-        S = a.samples or 8
+        m, B, S = a.m or 1024, a.batch or 256, a.samples or 32
         nets = [W.torus(L=4, D=16, seed=2 + b) for b in range(B)]
-        name = f"torus4x4_D16_fp32_uniform_m{m}"
-        dtype = "float32"
-    else:
-        m = a.m or 256
-        B = a.batch or 64
-        S = a.samples or 64
-        nets = [W.triangle(64, seed=1 + b) for b in range(B)]
-        name = f"triangle64_fp64_normal_m{m}"
-        dtype = "float64"
-    return nets, m, S, name, dtype
+        return nets, m, S, f"torus4x4_D16_fp32_uniform_m{m}_x{B}", "float32", "cyclic"
+    if a.workload == "batched":
+        m, B, S = a.m or 1024, a.batch or 4096, a.samples or 16
+        nets = W.random_batch(count=B, seed=4)
+        return nets, m, S, f"random_cyclic_3to12_bond2to32_fp32_m{m}_x{B}", "float32", "cyclic"
+    if a.workload == "ttcat":
+        m, B, S = a.m or 4096, a.batch or 1, a.samples or 4096
+        nets = [W.tt_caterpillar(seed=3 + b) for b in range(B)]
+        return nets, m, S, f"tt_caterpillar32_bond64_phys64_fp32_m{m}_x{B}", "float32", "acyclic"
+    m, B, S = a.m or 256, a.batch or 64, a.samples or 256
+    nets = [W.triangle(64, seed=1 + b) for b in range(B)]
+    return nets, m, S, f"triangle64_fp64_normal_m{m}_x{B}", "float64", "cyclic"
+
+
+def _oracle_net(workload):
+    import tn_workloads as W
+    return {"torus": lambda: W.torus(L=4, D=16, seed=2), "batched": lambda: W.random_network(4, 0),
+            "ttcat": lambda: W.tt_caterpillar(seed=3), "triangle": lambda: W.triangle(64, seed=1)}[workload]()
 
 
 def _cpu_worker(args):
-    workload, m, seed, samples = args
+    workload, m, samples = args
     import oracle
-    import tn_workloads as W
-    net = W.torus(L=4, D=16, seed=2) if workload == "torus" else W.triangle(64, seed=1)
+    net = _oracle_net(workload)
     t0 = time.perf_counter()
     for r in samples:
-        oracle.m1_estimate(net, m, seed, r, combine="dft")
+        if workload == "ttcat":
+            oracle.m2_estimate(net, m, 0, r)
+        else:
+            oracle.m1_estimate(net, m, 0, r, combine="dft")
     return len(samples), time.perf_counter() - t0
 
 
 def cpu_baseline(workload, m, seconds):
-    """The FP64 oracle (Eq. (1) with its DFT) on the host cores: one process per
-    core, each timing sketch estimates of one network for ~`seconds`."""
+    """The FP64 oracle on the host cores (one process per core, each computing
+    sketch estimates of one network of the workload for about `seconds`)."""
     import oracle
-    import tn_workloads as W
     oracle.build()
-    net = W.torus(L=4, D=16, seed=2) if workload == "torus" else W.triangle(64, seed=1)
     t0 = time.perf_counter()
-    oracle.m1_estimate(net, m, 0, 0, combine="dft")
+    _cpu_worker((workload, m, [0]))
     one = max(time.perf_counter() - t0, 1e-6)
     cores = max(1, min(16, os.cpu_count() or 1))
     per = max(1, int(seconds / one))
-    jobs = [(workload, m, 0, list(range(c * per, (c + 1) * per))) for c in range(cores)]
+    jobs = [(workload, m, list(range(c * per, (c + 1) * per))) for c in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("spawn").Pool(cores) as pool:
         res = pool.map(_cpu_worker, jobs)
     wall = time.perf_counter() - t0
     n = sum(r[0] for r in res)
+    how = "Method 2, Alg. 2-5" if workload == "ttcat" else "Eq. (1) with its DFT"
     return {"value": n / wall, "unit": "estimates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} estimates of one {workload} network (m={m}, FP64, DFT combine), "
+            "sample": f"{n} estimates of one {workload} network (m={m}, FP64, {how}), "
                       f"{per} per process on {cores} processes, {wall:.1f} s wall"}
+
+
+def measured_traffic(workload_name, samples_per_pass, kernel_source):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on this workload, schedule and kernel source."""
+    import glob
+    import hashlib
+    h = hashlib.sha256(open(os.path.join(ROOT, kernel_source), "rb").read()).hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(path):
+            if not line.startswith("machine-readable:"):
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:] if "=" in tok)
+            if (kv.get("workload") == workload_name and kv.get("samples_per_pass") == str(samples_per_pass)
+                    and kv.get("kernel_source_sha256_16") == h):
+                return float(kv["traffic_bytes_per_launch"]), os.path.basename(path)
+    return None, None
 
 
 def main():
@@ -108,7 +153,10 @@ def main():
     import torch
     import paper_2603_07387_amd as T
     torch.cuda.set_device(0)
-    nets, m, S, name, dtype = build_workload(a)
+    if a.copy_calibration:
+        copy_calibration()
+        return
+    nets, m, S, name, dtype, method = build_workload(a)
     td = getattr(torch, dtype)
     specs = []
     for n in nets:
@@ -116,7 +164,8 @@ def main():
         specs.append(T.NetworkSpec.from_network(n, ts))
     torch.cuda.synchronize()
     flags = T.TN_FLAG_PROFILE | (0 if os.environ.get("TN_SCATTER_SB") else T.TN_FLAG_AUTOTUNE)
-    plan = T.Plan(specs, T.TN_CYCLIC, m, S, 0, flags=flags)
+    meth = T.TN_CYCLIC if method == "cyclic" else T.TN_ACYCLIC
+    plan = T.Plan(specs, meth, m, S, 0, flags=flags)
     stats = torch.empty(2 * len(nets), dtype=torch.float64, device="cuda")
     for _ in range(a.warmup):
         plan.estimate(stats)
@@ -129,23 +178,43 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = wall * 1e3 / a.steps
-    est_total = len(nets) * S * a.steps
-    value = est_total / wall
+    value = len(nets) * S * a.steps / wall
     sk_ms, sk_n = plan.kernel_time(T.TN_KERNEL_SKETCH)
     kt = {"hash": plan.kernel_time(T.TN_KERNEL_HASH), "combine": plan.kernel_time(T.TN_KERNEL_COMBINE),
           "stats": plan.kernel_time(T.TN_KERNEL_STATS)}
-    # Algorithmic bytes of one sketching launch: every tensor entry once per pass of
-    # `sb` samples, the packed hash tables of each sample, the m-float sketch of
-    # each (slot, sample).
+    avg_ms = sk_ms / max(1, sk_n)
     entries = sum(n.nnz() for n in nets)
     esize = np.dtype(dtype).itemsize
-    W_ = plan.query(0)
-    sb, chunk = plan.query(8), plan.query(9)
-    passes = -(-chunk // sb)
-    sketch_bytes = plan.query(6) * m * (8 if dtype == "float64" else 4)
-    launch_bytes = passes * entries * esize + chunk * W_ * 4 + chunk * sketch_bytes
-    avg_ms = sk_ms / max(1, sk_n)
-    achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    if method == "cyclic":
+        # Algorithmic bytes of one sketching launch: every tensor entry once per
+        # pass of `sb` samples, the packed hash tables of each sample, the m-word
+        # sketch of each (slot, sample).
+        sb, chunk = plan.query(8), plan.query(9)
+        passes = -(-chunk // sb)
+        sketch_bytes = plan.query(6) * m * (8 if dtype == "float64" else 4)
+        launch_units = passes * entries * esize + chunk * plan.query(0) * 4 + chunk * sketch_bytes
+        achieved = launch_units / (avg_ms * 1e-3) / 1e9
+        traffic, tsrc = measured_traffic(name, sb, "paper_2603_07387_amd/csrc/m1.hip")
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
+                "kernel": "m1_scatter_kernel",
+                "avg_launch_ms": avg_ms, "launches": sk_n, "algorithmic_bytes_per_launch": launch_units,
+                "samples_per_pass": sb}
+    else:
+        # One GEMM launch per tree depth: 2 * rows * cols * samples flops of
+        # w_k = mat(X_k) G for every tensor with children at that depth.
+        flops_step = 2.0 * sum((n.nnz() - sum(int(np.prod(n.shape(k))) for k in range(n.p)
+                                               if len(n.shape(k)) == 1 and k != 0)) for n in nets) * S
+        achieved = flops_step / (sk_ms / a.steps * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VALU_PEAK_TFLOPS, "traffic": None, "kernel": "m2_gemm_kernel",
+                "avg_launch_ms": avg_ms, "launches": sk_n, "flops_per_step": flops_step}
+    st = stats.cpu().numpy().reshape(-1, 2)
+    norms = np.array([n.input_norm() for n in nets])
+    # input-relative std of one estimate (Def. 4's error scale), and the samples
+    # a network needs for a mean within 1e-2 of it (one standard error)
+    rel_std = np.sqrt(np.maximum(st[:, 1], 0)) / norms
+    need = np.maximum(1.0, np.ceil((rel_std / 1e-2) ** 2))
     out = {
         "metric": METRIC,
         "value": value,
@@ -159,14 +228,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if dtype == "float32" else "f64",
         "data": "synthetic",
-        "config": {"workload": name, "networks": len(nets), "samples_per_network": S, "m": m,
-                   "entries": entries, "bytes_resident": entries * esize},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "m1_scatter", "avg_launch_ms": avg_ms, "launches": sk_n,
-                     "algorithmic_bytes_per_launch": launch_bytes, "samples_per_pass": sb},
-        "kernel_ms_per_step": {"sketch": sk_ms / a.steps,
-                               **{k: v[0] / a.steps for k, v in kt.items()}},
+        "config": {"workload": name, "method": method, "networks": len(nets),
+                   "samples_per_network": S, "m": m, "entries": entries,
+                   "bytes_resident": entries * esize},
+        "roofline": roof,
+        "at_1e-2": {"median_input_relative_std": float(np.median(rel_std)),
+                    "median_samples_needed": float(np.median(need)),
+                    "networks_per_s": float(len(nets) / np.sum(need) * value)},
+        "kernel_ms_per_step": {"sketch": sk_ms / a.steps, **{k: v[0] / a.steps for k, v in kt.items()}},
     }
     plan.close()
     if not a.no_cpu_baseline:

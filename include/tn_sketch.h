@@ -106,7 +106,8 @@ typedef struct tn_plan tn_plan;
  *                  here, it is bound by each tn_sketch_estimate call).
  *   method       : TN_CYCLIC (any network) or TN_ACYCLIC (trees only).
  *   m            : sketch size (the paper's m), a power of two,
- *                  1 <= m <= 16384 for TN_CYCLIC, 2 <= m <= 65536 for TN_ACYCLIC.
+ *                  1 <= m <= 16384 for TN_CYCLIC (8192 with TN_F64 data),
+ *                  2 <= m <= 8192 for TN_ACYCLIC.
  *   samples      : S >= 1 independent sketch samples per network; sample r
  *                  uses hash key (seed + j, r, stream) for network j.
  *   root         : TN_ACYCLIC root tensor o (Algorithm 2), same for every
@@ -117,7 +118,10 @@ typedef struct tn_plan tn_plan;
  *                  memory until tn_plan_destroy.
  * Errors: TN_ERR_ARG, TN_ERR_DIMS, TN_ERR_HYPEREDGE, TN_ERR_SELFLOOP,
  * TN_ERR_CYCLIC, TN_ERR_PARTIAL, TN_ERR_UNSUPPORTED (mode size > 2^20,
- * order > 16, m outside the limits), TN_ERR_OOM, TN_ERR_HIP.
+ * order > 16, m outside the limits; TN_CYCLIC: a tensor whose last mode
+ * exceeds 1024; TN_ACYCLIC: a tensor with more than 8 children or whose child
+ * modes sum to more than 4096), TN_ERR_OOM, TN_ERR_HIP.
+ * Entries must be finite.
  * Uses the current HIP device; the plan is bound to it.
  */
 int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64_t m,
@@ -195,7 +199,8 @@ int tn_plan_set_hashes(tn_plan *plan, const int32_t *tables, void *stream);
  * doubles, sample-major, slots as in tn_plan_query key 6).  TN_CYCLIC: y_k =
  * T_k vec(X_k) for every tensor (Algorithm 1's x_k before the DFT).
  * TN_ACYCLIC: x_l = C_{k,l} mat(X_l) R_l^T r_l for each non-root tensor l and
- * x_o = R_o vec(X_o) in the root's slot (Algorithm 2).
+ * r_o = Q_o(kron_l x_l) in the root's slot (Algorithm 2; the estimate is
+ * x_o^T r_o).
  */
 int tn_plan_get_sketches(tn_plan *plan, const tn_network *nets, int64_t first, int64_t count,
                          void *stream, double *out);

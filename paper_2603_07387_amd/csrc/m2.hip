@@ -26,8 +26,8 @@
 //               scatter of the children's Kronecker products into an LDS
 //               fixed-point sketch r_k, then the gather g over the child index
 //               space, written to HBM.
-//   m2_gemm   : w_k = mat(X_k) G over all samples of the chunk (FP32 operands,
-//               FP64 accumulation), rows tiled by 64, samples by 64.
+//   m2_gemm   : w_k = mat(X_k) G over all samples of the chunk (operands in the
+//               storage type, FP64 accumulation), rows tiled by 64, samples by 64.
 #include <algorithm>
 #include <new>
 #include <queue>
