@@ -213,6 +213,15 @@ int tn_plan_get_sketches(tn_plan *plan, const tn_network *nets, int64_t first, i
  */
 int tn_plan_kernel_time(tn_plan *plan, int32_t kind, double *ms, int64_t *launches);
 
+/*
+ * tn_tensor_stats -- per-tensor statistics used as features by the sketch-size
+ * selector: for every tensor of every network (network-major, tensor order),
+ * four doubles sum x, sum x^2 (= ||X_k||_F^2), sum |x| and the count of entries
+ * >= 0, written to `out` (HOST, 4 * total tensors doubles).  All networks must
+ * share one dtype.  Synchronizes `stream`.
+ */
+int tn_tensor_stats(const tn_network *nets, int32_t n_nets, void *stream, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -14,5 +14,7 @@ from ._binding import (  # noqa: F401
     TN_KERNEL_COMBINE, TN_KERNEL_STATS, TNError, NetworkSpec, Plan, lib_path, load,
     tn_sketch_plan, tn_sketch_estimate, tn_contract_exact, tn_plan_destroy, tn_last_error,
     tn_plan_query, tn_plan_stream, tn_plan_get_hashes, tn_plan_set_hashes, tn_plan_get_sketches,
-    tn_plan_kernel_time,
+    tn_plan_kernel_time, MLP, tn_mlp_create, tn_mlp_num_params, tn_mlp_get_params,
+    tn_mlp_set_params, tn_mlp_predict, tn_mlp_grad, tn_mlp_step, tn_mlp_train, tn_mlp_destroy,
+    tn_tensor_stats,
 )

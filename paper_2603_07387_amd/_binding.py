@@ -214,6 +214,137 @@ def tn_plan_kernel_time(plan, kind):
     return ms.value, n.value
 
 
+def tn_tensor_stats(specs, stream=None):
+    """Per tensor [sum x, sum x^2, sum |x|, #(x >= 0)] as a numpy (tensors, 4) array."""
+    import numpy as np
+    L = load()
+    L.tn_tensor_stats.argtypes = [ctypes.POINTER(tn_network), ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_double)]
+    nt = sum(s.p for s in specs)
+    out = np.zeros(nt * 4, dtype=np.float64)
+    _check(L.tn_tensor_stats(_array(specs), len(specs), _stream(stream),
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(nt, 4)
+
+
+def _mlp_lib():
+    L = load()
+    if getattr(L, "_mlp_ready", False):
+        return L
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.tn_mlp_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, P(vp)]
+    L.tn_mlp_num_params.argtypes = [vp]
+    L.tn_mlp_num_params.restype = ctypes.c_int64
+    L.tn_mlp_get_params.argtypes = [vp, P(ctypes.c_float)]
+    L.tn_mlp_set_params.argtypes = [vp, P(ctypes.c_float)]
+    L.tn_mlp_predict.argtypes = [vp, vp, ctypes.c_int64, vp, vp]
+    L.tn_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp, P(ctypes.c_double)]
+    L.tn_mlp_step.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_float, vp]
+    L.tn_mlp_train.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                               ctypes.c_float, vp, P(ctypes.c_double)]
+    L.tn_mlp_destroy.argtypes = [vp]
+    L.tn_mlp_destroy.restype = None
+    L._mlp_ready = True
+    return L
+
+
+def tn_mlp_create(d_in, hidden, seed):
+    h = ctypes.c_void_p()
+    _check(_mlp_lib().tn_mlp_create(d_in, hidden, seed, ctypes.byref(h)))
+    return h
+
+
+def tn_mlp_num_params(net):
+    return int(_check(_mlp_lib().tn_mlp_num_params(net)))
+
+
+def tn_mlp_get_params(net):
+    import numpy as np
+    out = np.zeros(tn_mlp_num_params(net), dtype=np.float32)
+    _check(_mlp_lib().tn_mlp_get_params(net, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def tn_mlp_set_params(net, params):
+    import numpy as np
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_mlp_lib().tn_mlp_set_params(net, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+
+def tn_mlp_predict(net, X, stream, out):
+    return _check(_mlp_lib().tn_mlp_predict(net, _ptr(X), X.shape[0], _stream(stream), _ptr(out)))
+
+
+def tn_mlp_grad(net, X, y, stream, grad):
+    loss = ctypes.c_double()
+    _check(_mlp_lib().tn_mlp_grad(net, _ptr(X), _ptr(y), X.shape[0], _stream(stream), _ptr(grad),
+                                  ctypes.byref(loss)))
+    return loss.value
+
+
+def tn_mlp_step(net, X, y, lr, stream=None):
+    return _check(_mlp_lib().tn_mlp_step(net, _ptr(X), _ptr(y), X.shape[0], lr, _stream(stream)))
+
+
+def tn_mlp_train(net, X, y, batch, epochs, lr, stream=None, want_losses=True):
+    import numpy as np
+    losses = np.zeros(max(1, epochs), dtype=np.float64) if want_losses else None
+    _check(_mlp_lib().tn_mlp_train(
+        net, _ptr(X), _ptr(y), X.shape[0], batch, epochs, lr, _stream(stream),
+        losses.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if losses is not None else None))
+    return losses[:epochs] if losses is not None else None
+
+
+def tn_mlp_destroy(net):
+    _mlp_lib().tn_mlp_destroy(net)
+
+
+class MLP:
+    """Owns a tn_mlp handle (3-layer tanh perceptron, FP32, device kernels)."""
+
+    def __init__(self, d_in, hidden=64, seed=0):
+        self.d_in, self.hidden = d_in, hidden
+        self.handle = tn_mlp_create(d_in, hidden, seed)
+
+    @property
+    def num_params(self):
+        return tn_mlp_num_params(self.handle)
+
+    def params(self):
+        return tn_mlp_get_params(self.handle)
+
+    def set_params(self, p):
+        tn_mlp_set_params(self.handle, p)
+
+    def predict(self, X, stream=None):
+        out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        tn_mlp_predict(self.handle, X, stream, out)
+        return out
+
+    def grad(self, X, y, stream=None):
+        g = torch.empty(self.num_params, dtype=torch.float32, device=X.device)
+        loss = tn_mlp_grad(self.handle, X, y, stream, g)
+        return g, loss
+
+    def step(self, X, y, lr, stream=None):
+        tn_mlp_step(self.handle, X, y, lr, stream)
+
+    def train(self, X, y, batch=4096, epochs=100, lr=1e-3, stream=None):
+        return tn_mlp_train(self.handle, X, y, batch, epochs, lr, stream)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            tn_mlp_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """Owns a tn_plan handle; thin methods over the C calls."""
 
