@@ -27,7 +27,11 @@ typedef struct tn_mlp tn_mlp;
 
 /* Create a network with d_in inputs (1..256) and H hidden units (1..128),
  * parameters drawn Glorot-uniform from a SplitMix64 stream keyed by seed, biases
- * zero, Adam moments zero.  Errors: TN_ERR_ARG, TN_ERR_OOM, TN_ERR_HIP. */
+ * zero, Adam moments zero.  A block keeps all parameters and the activations of
+ * 64 rows in LDS: 4 (n_params + 64 d_in + 256 H + 66) bytes, which must leave 1 KiB
+ * of the device's per-block LDS free (160 KiB on gfx950: d_in 20 with H 64 takes
+ * 93 KB; H 96 allows d_in up to 40), else TN_ERR_UNSUPPORTED.
+ * Errors: TN_ERR_ARG, TN_ERR_OOM, TN_ERR_HIP, TN_ERR_UNSUPPORTED. */
 int tn_mlp_create(int32_t d_in, int32_t hidden, uint64_t seed, tn_mlp **out);
 
 /* Number of parameters. */
@@ -39,7 +43,7 @@ int tn_mlp_get_params(const tn_mlp *net, float *host_out);
 int tn_mlp_set_params(tn_mlp *net, const float *host_in);
 
 /* Predictions for n rows of X (DEVICE, n x d_in FP32 row-major) into out
- * (DEVICE, n FP32). */
+ * (DEVICE, n FP32).  n = 0 does nothing (X and out may then be NULL). */
 int tn_mlp_predict(tn_mlp *net, const float *X, int64_t n, void *stream, float *out);
 
 /* Loss 0.5 mean((f(X) - y)^2) over n rows and its gradient with respect to the

@@ -222,6 +222,18 @@ int tn_plan_kernel_time(tn_plan *plan, int32_t kind, double *ms, int64_t *launch
  */
 int tn_tensor_stats(const tn_network *nets, int32_t n_nets, void *stream, double *out);
 
+/*
+ * tn_median_of_means -- the amplification of Theorem 1: per network, split its
+ * S per-sample estimates (samples: DEVICE, n_nets * S doubles, network-major, as
+ * written by tn_sketch_estimate's samples_out) into `groups` consecutive groups,
+ * group g holding samples [floor(g S / G), floor((g + 1) S / G)), and write the
+ * median of the G group means to out (DEVICE, n_nets doubles; for even G the
+ * mean of the two middle ones; NaN if any group mean is NaN).  FP64.
+ * 1 <= groups <= min(S, 1024), else TN_ERR_ARG.  Asynchronous on `stream`.
+ */
+int tn_median_of_means(const double *samples, int64_t n_nets, int64_t S, int32_t groups,
+                       void *stream, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@ Functions (each cites the passage of arXiv 2603.07387 it follows):
   * ``m2_estimate``   -- Method 2, Eq. (2) / Algorithms 2-5, per sample
   * ``dft``/``fft``/``circ_conv`` -- Def. 8 and the DFT convention of Lemma 5's proof
   * ``mean_var``      -- Welford sample mean / unbiased variance
+  * ``median_of_means`` -- the median amplification of Theorem 1
 """
 from __future__ import annotations
 
@@ -303,6 +304,15 @@ def circ_conv(x, y):
     out = np.zeros(len(x))
     lib().orc_circ_conv(len(x), _dptr(x), _dptr(y), _dptr(out))
     return out
+
+
+def median_of_means(x, groups):
+    """Median of the means of `groups` consecutive groups of x, group g holding
+    x[floor(g S / G) : floor((g + 1) S / G)] (the amplification of Theorem 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    S = len(x)
+    means = [float(np.mean(x[g * S // groups:(g + 1) * S // groups])) for g in range(groups)]
+    return float(np.median(means))
 
 
 def mean_var(x):

@@ -90,6 +90,8 @@ def load():
     L.tn_plan_get_sketches.restype = ctypes.c_int
     L.tn_plan_kernel_time.argtypes = [vp, i32, P(ctypes.c_double), P(i64)]
     L.tn_plan_kernel_time.restype = ctypes.c_int
+    L.tn_median_of_means.argtypes = [vp, i64, i64, i32, vp, vp]
+    L.tn_median_of_means.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -225,6 +227,19 @@ def tn_tensor_stats(specs, stream=None):
     _check(L.tn_tensor_stats(_array(specs), len(specs), _stream(stream),
                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out.reshape(nt, 4)
+
+
+def tn_median_of_means(samples, n_nets, S, groups, stream, out):
+    return _check(load().tn_median_of_means(_ptr(samples), n_nets, S, groups, _stream(stream), _ptr(out)))
+
+
+def median_of_means(samples, groups, stream=None):
+    """Median of `groups` group means per row of a (n_nets, S) float64 device tensor."""
+    if samples.dim() != 2 or samples.dtype != torch.float64 or not samples.is_contiguous():
+        raise ValueError("samples must be a contiguous (n_nets, S) float64 tensor")
+    out = torch.empty(samples.shape[0], dtype=torch.float64, device=samples.device)
+    tn_median_of_means(samples, samples.shape[0], samples.shape[1], groups, stream, out)
+    return out
 
 
 def _mlp_lib():

@@ -25,7 +25,7 @@ struct tn_mlp {
   float *d_m = nullptr, *d_v = nullptr;
   double *d_partial = nullptr;  // [blocks][P + 1]
   int64_t partial_blocks = 0;
-  double *d_scalar = nullptr;   // loss of the last reduction
+  double *d_scalar = nullptr;   // [0] loss of the last reduction, [1] running epoch loss
   int64_t t = 0;                // Adam steps taken
   size_t lds = 0;
 };
@@ -134,17 +134,20 @@ __global__ __launch_bounds__(256) void mlp_fwd_bwd_kernel(
   }
 }
 
-// mode 0: grad[p] = sum; mode 1: Adam.  scalar[0] = summed loss * loss_scale.
+// mode 0: grad[p] = sum; mode 1: Adam.  scalar[0] = summed loss * loss_scale and
+// scalar[1] += summed loss * epoch_scale (the epoch's mean loss, batch by batch).
 __global__ void mlp_reduce_kernel(const double *__restrict__ partial, int64_t blocks, int64_t P,
                                   int mode, float *__restrict__ grad, float *__restrict__ params,
                                   float *__restrict__ m, float *__restrict__ v, float lr, float c1,
-                                  float c2, double loss_scale, double *__restrict__ scalar) {
+                                  float c2, double loss_scale, double epoch_scale,
+                                  double *__restrict__ scalar) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p > P) return;
   double g = 0.0;
   for (int64_t b = 0; b < blocks; ++b) g += partial[b * (P + 1) + p];
   if (p == P) {
     scalar[0] = g * loss_scale;
+    scalar[1] += g * epoch_scale;
     return;
   }
   if (mode == 0) {
@@ -196,7 +199,8 @@ int fwd_bwd(tn_mlp *net, const float *X, const float *y, int64_t row0, int64_t r
   return TN_OK;
 }
 
-int reduce(tn_mlp *net, int64_t rows, int mode, float *grad, float lr, hipStream_t st) {
+int reduce(tn_mlp *net, int64_t rows, int mode, float *grad, float lr, hipStream_t st,
+           double epoch_scale = 0.0) {
   const int64_t blocks = (rows + kRows - 1) / kRows;
   float c1 = 1.f, c2 = 1.f;
   if (mode == 1) {
@@ -207,7 +211,7 @@ int reduce(tn_mlp *net, int64_t rows, int mode, float *grad, float lr, hipStream
   const unsigned g = (unsigned)((net->P + 1 + 255) / 256);
   hipLaunchKernelGGL(mlp_reduce_kernel, dim3(g), dim3(256), 0, st, net->d_partial, blocks, net->P,
                      mode, grad, net->d_params, net->d_m, net->d_v, lr, c1, c2,
-                     1.0 / (double)rows, net->d_scalar);
+                     1.0 / (double)rows, epoch_scale, net->d_scalar);
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }
@@ -265,7 +269,7 @@ int tn_mlp_create(int32_t d_in, int32_t hidden, uint64_t seed, tn_mlp **out) {
   bool ok = hipMalloc((void **)&net->d_params, (size_t)net->P * 4) == hipSuccess &&
             hipMalloc((void **)&net->d_m, (size_t)net->P * 4) == hipSuccess &&
             hipMalloc((void **)&net->d_v, (size_t)net->P * 4) == hipSuccess &&
-            hipMalloc((void **)&net->d_scalar, 8) == hipSuccess;
+            hipMalloc((void **)&net->d_scalar, 16) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     tn_mlp_destroy(net);
@@ -273,7 +277,8 @@ int tn_mlp_create(int32_t d_in, int32_t hidden, uint64_t seed, tn_mlp **out) {
   }
   if (hipMemcpy(net->d_params, h.data(), (size_t)net->P * 4, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(net->d_m, 0, (size_t)net->P * 4) != hipSuccess ||
-      hipMemset(net->d_v, 0, (size_t)net->P * 4) != hipSuccess) {
+      hipMemset(net->d_v, 0, (size_t)net->P * 4) != hipSuccess ||
+      hipMemset(net->d_scalar, 0, 16) != hipSuccess) {
     tn_mlp_destroy(net);
     return set_error(TN_ERR_HIP, "mlp: initial upload");
   }
@@ -308,7 +313,9 @@ int tn_mlp_set_params(tn_mlp *net, const float *host_in) {
 
 int tn_mlp_predict(tn_mlp *net, const float *X, int64_t n, void *stream, float *out) {
   clear_error();
-  if (!net || !X || !out || n < 0) return set_error(TN_ERR_ARG, "bad argument");
+  if (!net || n < 0) return set_error(TN_ERR_ARG, "bad argument");
+  if (n == 0) return TN_OK;
+  if (!X || !out) return set_error(TN_ERR_ARG, "null X or out");
   return fwd_bwd(net, X, nullptr, 0, n, n, (hipStream_t)stream, out, false);
 }
 
@@ -341,20 +348,17 @@ int tn_mlp_train(tn_mlp *net, const float *X, const float *y, int64_t n, int32_t
   if (!net || !X || !y || n < 1 || batch < 1 || epochs < 0) return set_error(TN_ERR_ARG, "bad argument");
   hipStream_t st = (hipStream_t)stream;
   for (int ep = 0; ep < epochs; ++ep) {
-    double total = 0.0;
+    if (losses) TN_HIP_CHECK(hipMemsetAsync(net->d_scalar + 1, 0, 8, st));
     for (int64_t r0 = 0; r0 < n; r0 += batch) {
       const int64_t rows = std::min<int64_t>(batch, n - r0);
       int rc = fwd_bwd(net, X, y, r0, rows, n, st, nullptr, true);
-      if (rc == TN_OK) rc = reduce(net, rows, 1, nullptr, lr, st);
+      if (rc == TN_OK) rc = reduce(net, rows, 1, nullptr, lr, st, 1.0 / (double)n);
       if (rc != TN_OK) return rc;
-      if (losses) {
-        double l = 0.0;
-        TN_HIP_CHECK(hipMemcpyAsync(&l, net->d_scalar, 8, hipMemcpyDeviceToHost, st));
-        TN_HIP_CHECK(hipStreamSynchronize(st));
-        total += l * (double)rows;
-      }
     }
-    if (losses) losses[ep] = total / (double)n;
+    if (losses) {
+      TN_HIP_CHECK(hipMemcpyAsync(&losses[ep], net->d_scalar + 1, 8, hipMemcpyDeviceToHost, st));
+      TN_HIP_CHECK(hipStreamSynchronize(st));
+    }
   }
   return TN_OK;
 }

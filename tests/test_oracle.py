@@ -293,6 +293,23 @@ def test_mean_var(orc):
     assert var == pytest.approx(x.var(ddof=1), rel=1e-12)
 
 
+def test_median_of_means_special_cases(orc):
+    import statistics
+    # a worked case: S = 7, G = 3 -> groups [0,2) [2,4) [4,7)
+    x = [1.0, 3.0, 10.0, 20.0, -4.0, 0.0, 1.0]
+    assert orc.median_of_means(x, 3) == 2.0          # means 2, 15, -1 -> median 2
+    # even G: the mean of the two middle group means
+    assert orc.median_of_means([5.0, 1.0, 3.0, 100.0], 4) == 4.0
+    rng = np.random.default_rng(9)
+    y = rng.standard_normal(101)
+    assert orc.median_of_means(y, 1) == pytest.approx(float(np.mean(y)), rel=1e-14)
+    assert orc.median_of_means(y, 101) == statistics.median(y.tolist())
+    # the median ignores one wild group that the mean does not
+    z = np.ones(90)
+    z[:10] = 1e6
+    assert orc.median_of_means(z, 9) == 1.0
+
+
 # --------------------------------------------------------------------------
 # Method 2
 # --------------------------------------------------------------------------
