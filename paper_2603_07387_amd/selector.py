@@ -325,25 +325,43 @@ def choose(net, method, logv, eps=1e-2, z=2.0, max_samples=1 << 20, st=None):
 
 class Selector:
     """The learned selector: an MLP on the library's kernels predicting the
-    standardized label, with the standardization kept here."""
+    standardized label, with the standardization and a calibration margin kept
+    here.  The margin is the `quantile` of (label - prediction) over networks
+    held out of training, added to every predicted log v(m): predictions then
+    fall below the measured label for about 1 - quantile of unseen networks."""
 
     def __init__(self, hidden=64, seed=0):
         self.mlp = B.MLP(D_IN, hidden, seed=seed)
         self.hidden = hidden
-        self.mu, self.sd = 0.0, 1.0
+        self.mu, self.sd, self.margin = 0.0, 1.0, 0.0
 
-    def fit(self, X, y, epochs=400, lr=2e-3, batch=4096, seed=0):
-        self.mu, self.sd = float(np.mean(y)), float(np.std(y)) or 1.0
-        perm = np.random.default_rng(seed).permutation(len(y))
-        Xt = torch.from_numpy(np.ascontiguousarray(X[perm])).cuda()
-        yt = torch.from_numpy(((y[perm] - self.mu) / self.sd).astype(np.float32)).cuda()
-        return self.mlp.train(Xt, yt, batch=batch, epochs=epochs, lr=lr)
+    def fit(self, X, y, groups=None, epochs=400, lr=2e-3, batch=4096, seed=0, calib_frac=0.1,
+            quantile=0.9):
+        """Train on X, y; rows sharing a `groups` id (a network) stay on one side
+        of the calibration split.  Returns the per-epoch training losses."""
+        rng = np.random.default_rng(seed)
+        groups = np.arange(len(y)) if groups is None else np.asarray(groups)
+        ids = np.unique(groups)
+        calib = np.isin(groups, rng.permutation(ids)[:int(len(ids) * calib_frac)]) if calib_frac > 0 \
+            else np.zeros(len(y), dtype=bool)
+        Xt, yt = X[~calib], y[~calib]
+        self.mu, self.sd = float(np.mean(yt)), float(np.std(yt)) or 1.0
+        perm = rng.permutation(len(yt))
+        Xd = torch.from_numpy(np.ascontiguousarray(Xt[perm])).cuda()
+        yd = torch.from_numpy(((yt[perm] - self.mu) / self.sd).astype(np.float32)).cuda()
+        losses = self.mlp.train(Xd, yd, batch=batch, epochs=epochs, lr=lr)
+        self.margin = 0.0
+        if calib.any():
+            self.margin = max(0.0, float(np.quantile(y[calib] - self.predict(X[calib], raw=True), quantile)))
+        return losses
 
-    def predict(self, X):
+    def predict(self, X, raw=False):
+        """Predicted log v for feature rows X (with the calibration margin
+        unless raw)."""
         if len(X) == 0:
             return np.zeros(0)
         out = self.mlp.predict(torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda())
-        return out.cpu().numpy().astype(np.float64) * self.sd + self.mu
+        return out.cpu().numpy().astype(np.float64) * self.sd + self.mu + (0.0 if raw else self.margin)
 
     def logv(self, net, stats, method, st=None):
         st = st or _structure(net)
@@ -355,7 +373,8 @@ class Selector:
         return choose(net, method, self.logv(net, stats, method, st), eps, z, st=st)
 
     def save(self, path):
-        np.savez(path, params=self.mlp.params(), mu=self.mu, sd=self.sd, hidden=self.hidden, d_in=D_IN)
+        np.savez(path, params=self.mlp.params(), mu=self.mu, sd=self.sd, margin=self.margin,
+                 hidden=self.hidden, d_in=D_IN)
 
     @classmethod
     def load(cls, path):
@@ -364,7 +383,7 @@ class Selector:
             raise ValueError("feature width differs")
         sel = cls(int(z["hidden"]))
         sel.mlp.set_params(z["params"])
-        sel.mu, sel.sd = float(z["mu"]), float(z["sd"])
+        sel.mu, sel.sd, sel.margin = float(z["mu"]), float(z["sd"]), float(z["margin"])
         return sel
 
 
@@ -446,21 +465,24 @@ def main(argv=None):
     X, y, idx = dataset(measured)
     t_data = time.time() - t0
     nets = len(measured)
-    val = np.random.default_rng(a.seed).permutation(nets)[:max(1, nets // 10)]
+    val = np.random.default_rng(a.seed + 1).permutation(nets)[:max(1, nets // 10)]
     is_val = np.isin(idx, val)
     sel = Selector(64, seed=a.seed)
     t1 = time.time()
-    losses = sel.fit(X[~is_val], y[~is_val], epochs=a.epochs, lr=a.lr, seed=a.seed)
+    losses = sel.fit(X[~is_val], y[~is_val], groups=idx[~is_val], epochs=a.epochs, lr=a.lr, seed=a.seed)
     torch.cuda.synchronize()
     t_train = time.time() - t1
-    val_rmse = float(np.sqrt(np.mean((sel.predict(X[is_val]) - y[is_val]) ** 2)))
-    _log(f"trained: {len(y)} rows, {a.epochs} epochs in {t_train:.2f} s, val rmse {val_rmse:.3f}")
+    val_rmse = float(np.sqrt(np.mean((sel.predict(X[is_val], raw=True) - y[is_val]) ** 2)))
+    val_cover = float(np.mean(sel.predict(X[is_val]) >= y[is_val]))
+    _log(f"trained: {len(y)} rows, {a.epochs} epochs in {t_train:.2f} s, val rmse {val_rmse:.3f}, "
+         f"margin {sel.margin:.3f}, val coverage {val_cover:.3f}")
     if a.save:
         sel.save(a.save)
     held = family_networks(a.held_out, a.seed + 1, held_out=True) + batch_networks(a.held_out_batch)
     rows = evaluate(sel, held, verbose=True)
     out = {"networks": nets, "tuples": int(len(y)), "data_seconds": t_data, "train_seconds": t_train,
            "final_train_loss_std_units": float(losses[-1]), "val_rmse_logv": val_rmse,
+           "margin": sel.margin, "val_coverage": val_cover,
            "label_std_logv": float(np.std(y)), "held_out": summarize(rows),
            "held_out_families": summarize([r for r in rows if not r["name"].startswith("rand4_")]),
            "held_out_batch": summarize([r for r in rows if r["name"].startswith("rand4_")])}
