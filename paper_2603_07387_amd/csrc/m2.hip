@@ -26,8 +26,10 @@
 //               scatter of the children's Kronecker products into an LDS
 //               fixed-point sketch r_k, then the gather g over the child index
 //               space, written to HBM.
-//   m2_gemm   : w_k = mat(X_k) G over all samples of the chunk (operands in the
-//               storage type, FP64 accumulation), rows tiled by 64, samples by 64.
+//   m2_gemm   : w_k = mat(X_k) G over all samples of the chunk on the FP64
+//               matrix cores (operands widened exactly, FP64 accumulation),
+//               blocks of 64 rows x 16 samples, columns optionally split over
+//               wave groups and summed in a fixed order.
 #include <algorithm>
 #include <new>
 #include <queue>
@@ -77,6 +79,7 @@ struct M2Plan {
   M2Node *d_nodes = nullptr;
   std::vector<std::vector<int32_t>> level_nodes;  // per depth: nodes with children
   std::vector<std::vector<M2Tile>> level_tiles;
+  std::vector<int64_t> level_maxcols;             // per depth: widest node
   std::vector<int32_t *> d_level_nodes;
   std::vector<M2Tile *> d_level_tiles;
   int64_t g_row = 0;    // entries of g per sample (max over depths)
@@ -91,9 +94,6 @@ struct M2Plan {
 
 namespace {
 
-constexpr int kTR = 64;   // GEMM rows per tile
-constexpr int kTS = 64;   // GEMM samples per tile
-constexpr int kTK = 32;   // GEMM columns per step
 
 template <typename T>
 __device__ __forceinline__ double load_val(const void *p, int64_t i);
@@ -114,6 +114,116 @@ __device__ __forceinline__ uint32_t sum_packed(uint32_t a, uint32_t b, uint32_t 
   return (((a & 0x7fffffffu) + (b & 0x7fffffffu)) & mask) | ((a ^ b) & 0x80000000u);
 }
 
+// Packed value of tensor sketch T_{tix}, side d, at an m-valued index: from the
+// injected tables or evaluated from the hash coefficients.
+__device__ __forceinline__ uint32_t tsketch(const M2Node &nd, const int32_t *tab,
+                                            const HashCoeffs *coef, int c, uint32_t m,
+                                            uint32_t mask, int tix, int d, uint32_t idx) {
+  if (tab) return (uint32_t)tab[nd.t_tab + (int64_t)(2 * tix + d) * m + idx];
+  return hash_packed(coef[c + 2 * tix + d], idx, mask);
+}
+
+// Both passes over the child index space of one (tensor, sample) for padded
+// order QT: the scatter r_k = R_k (kron_l w_l) into the fixed-point LDS sketch,
+// then the gather g[col] = sigma(col) r_k[b(col)].  A thread walks columns
+// col = tid + 256 i; the child index tuple (row-major over the children, the
+// last child fastest) advances by the mixed-radix digits of 256, so the loop
+// divides nothing and every array stays in registers.
+template <typename A, int QT>
+__device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const int32_t *tab_base,
+                                               const uint32_t *dtab, const double *wv,
+                                               unsigned long long *acc, const int32_t *tab,
+                                               const HashCoeffs *coef, uint32_t mask, uint32_t m,
+                                               double sc, double inv_sc, A *g) {
+  const int tid = threadIdx.x;
+  const uint32_t ncols = (uint32_t)nd.ncols;
+  uint32_t dim[QT], step[QT], idx0[QT];
+  int32_t tb[QT];
+  {
+    uint32_t col = (uint32_t)tid, st = 256u;
+#pragma unroll
+    for (int j = QT - 1; j >= 0; --j) {
+      tb[j] = tab_base[j];
+      if (j < c) {
+        dim[j] = (uint32_t)nd.child_dim[j];
+        idx0[j] = col % dim[j];
+        col /= dim[j];
+        step[j] = st % dim[j];
+        st /= dim[j];
+      } else {
+        dim[j] = 1u;
+        idx0[j] = 0u;
+        step[j] = 0u;
+      }
+    }
+    // the most significant digit absorbs what is left (it can exceed its
+    // radix only once the column is past the end)
+    if (c > 0) {
+      idx0[0] += col * dim[0];
+      step[0] += st * dim[0];
+    }
+  }
+  // Recursive-sketch hash (Algorithm 4) of a child index tuple.
+  auto rs_hash = [&](const uint32_t *idx) -> uint32_t {
+    uint32_t v[QT];
+#pragma unroll
+    for (int j = 0; j < QT; ++j) v[j] = dtab[tb[j] + (j < c ? (int32_t)idx[j] : 0)];
+    if constexpr (QT == 1) {
+      return v[0];
+    } else {
+      uint32_t b[QT / 2];
+#pragma unroll
+      for (int t = 0; t < QT / 2; ++t) b[t] = sum_packed(v[2 * t], v[2 * t + 1], mask);
+#pragma unroll
+      for (int l = QT / 2; l >= 2; l /= 2) {
+#pragma unroll
+        for (int t = 0; t < l / 2; ++t) {
+          const int tix = QT - l + t;
+          const uint32_t t0 = tsketch(nd, tab, coef, c, m, mask, tix, 0, b[2 * t] & 0x7fffffffu);
+          const uint32_t t1 = tsketch(nd, tab, coef, c, m, mask, tix, 1, b[2 * t + 1] & 0x7fffffffu);
+          const uint32_t sg = (b[2 * t] ^ b[2 * t + 1] ^ t0 ^ t1) & 0x80000000u;
+          b[t] = (((t0 & 0x7fffffffu) + (t1 & 0x7fffffffu)) & mask) | sg;
+        }
+      }
+      return b[0];
+    }
+  };
+  auto advance = [&](uint32_t *idx) {
+    uint32_t carry = 0u;
+#pragma unroll
+    for (int j = QT - 1; j >= 0; --j) {
+      if (j < c) {
+        const uint32_t v = idx[j] + step[j] + carry;
+        carry = v >= dim[j] && j > 0 ? 1u : 0u;
+        idx[j] = v - carry * dim[j];
+      }
+    }
+  };
+  const double kMagic = 6755399441055744.0;
+  uint32_t idx[QT];
+#pragma unroll
+  for (int j = 0; j < QT; ++j) idx[j] = idx0[j];
+  for (uint32_t col = (uint32_t)tid; col < ncols; col += 256u) {
+    const uint32_t h = rs_hash(idx);
+    double p = 1.0;
+#pragma unroll
+    for (int j = 0; j < QT; ++j)
+      if (j < c) p *= wv[tb[j] + (int32_t)idx[j]];
+    const long long v = __double_as_longlong(fma(p, sc, kMagic)) - __double_as_longlong(kMagic);
+    atomicAdd(&acc[h & mask], (unsigned long long)((h & 0x80000000u) ? -v : v));
+    advance(idx);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < QT; ++j) idx[j] = idx0[j];
+  for (uint32_t col = (uint32_t)tid; col < ncols; col += 256u) {
+    const uint32_t h = rs_hash(idx);
+    const double r = (double)(long long)acc[h & mask] * inv_sc;
+    g[col] = (A)((h & 0x80000000u) ? -r : r);
+    advance(idx);
+  }
+}
+
 // One sample's sketch r_k and gather g for tensor k (see the file comment).
 // A: storage type of w and g (float for FP32/BF16 data, double for FP64).
 template <typename T, typename A>
@@ -127,7 +237,7 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
   __shared__ unsigned long long wmax[kM2MaxChildren];
   __shared__ int32_t tab_base[kM2MaxChildren + 1];
 
-  const M2Node nd = nodes[level[blockIdx.x]];
+  const M2Node &nd = nodes[level[blockIdx.x]];
   const int64_t s = blockIdx.y;
   const uint64_t sample = (uint64_t)(sample0 + s);
   const int tid = threadIdx.x;
@@ -172,8 +282,7 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
 
   // Tensor-sketch lookup: packed value of T_{tix} side d at an m-valued index.
   auto tsk = [&](int tix, int d, uint32_t idx) -> uint32_t {
-    if (tab) return (uint32_t)tab[nd.t_tab + (int64_t)(2 * tix + d) * m + idx];
-    return hash_packed(coef[c + 2 * tix + d], idx, mask);
+    return tsketch(nd, tab, coef, c, m, mask, tix, d, idx);
   };
 
   // Level-one slot tables: the child (or padding) count sketch, followed by the
@@ -217,52 +326,13 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
   if (pmax > 0.0) (void)frexp(pmax, &e);
   const double sc = ldexp(1.0, 62 - lgN - e);
   const double inv_sc = ldexp(1.0, -(62 - lgN - e));
-  const double kMagic = 6755399441055744.0;
 
-  // Recursive-sketch hash (Algorithm 4) of the child index tuple of column col.
-  auto rs_hash = [&](int64_t col, int32_t *idx) -> uint32_t {
-    for (int j = c - 1; j >= 0; --j) {
-      idx[j] = (int32_t)(col % nd.child_dim[j]);
-      col /= nd.child_dim[j];
-    }
-    if (qt == 1) return dtab[idx[0]];
-    uint32_t b[kM2MaxChildren / 2];
-    for (int t = 0; t < qt / 2; ++t) {
-      const int jl = 2 * t, jr = 2 * t + 1;
-      const uint32_t vl = dtab[tab_base[jl] + (jl < c ? idx[jl] : 0)];
-      const uint32_t vr = dtab[tab_base[jr] + (jr < c ? idx[jr] : 0)];
-      b[t] = sum_packed(vl, vr, mask);
-    }
-    for (int l = qt / 2; l >= 2; l /= 2) {
-      for (int t = 0; t < l / 2; ++t) {
-        const int tix = qt - l + t;
-        const uint32_t t0 = tsk(tix, 0, b[2 * t] & 0x7fffffffu);
-        const uint32_t t1 = tsk(tix, 1, b[2 * t + 1] & 0x7fffffffu);
-        const uint32_t sg = (b[2 * t] ^ b[2 * t + 1] ^ t0 ^ t1) & 0x80000000u;
-        b[t] = (((t0 & 0x7fffffffu) + (t1 & 0x7fffffffu)) & mask) | sg;
-      }
-    }
-    return b[0];
-  };
-
-  // r_k = R_k (kron_l w_l): scatter of the products.
-  for (int64_t col = tid; col < nd.ncols; col += 256) {
-    int32_t idx[kM2MaxChildren];
-    const uint32_t h = rs_hash(col, idx);
-    double p = 1.0;
-    for (int j = 0; j < c; ++j) p *= wv[tab_base[j] + idx[j]];
-    const long long v = __double_as_longlong(fma(p, sc, kMagic)) - __double_as_longlong(kMagic);
-    atomicAdd(&acc[h & mask], (unsigned long long)((h & 0x80000000u) ? -v : v));
-  }
-  __syncthreads();
-
-  // g[col] = sigma(col) r_k[b(col)].
   A *g = gbuf + s * g_row + nd.g_off;
-  for (int64_t col = tid; col < nd.ncols; col += 256) {
-    int32_t idx[kM2MaxChildren];
-    const uint32_t h = rs_hash(col, idx);
-    const double r = (double)(long long)acc[h & mask] * inv_sc;
-    g[col] = (A)((h & 0x80000000u) ? -r : r);
+  switch (qt) {
+    case 1: gather_columns<A, 1>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+    case 2: gather_columns<A, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+    case 4: gather_columns<A, 4>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+    default: gather_columns<A, 8>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
   }
   if (r_out && nd.root) {
     for (uint32_t b = tid; b < m; b += 256)
@@ -270,70 +340,214 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
   }
 }
 
-// w_k[row] = sum_col X_k(row, col) g[col] for a tile of 64 rows x 64 samples.
-template <typename T, typename A>
-__global__ __launch_bounds__(256) void m2_gemm_kernel(
+// ---------------------------------------------------------------------------
+// w_k = mat(X_k) G on the FP64 matrix cores with v_mfma_f64_4x4x4f64: four
+// independent 4x4x4 blocks per instruction, lane layout (measured)
+//   A[b][i][k] in lane 16k + 4b + i,  B[b][k][j] in lane 16k + 4b + j,
+//   D[b][i][j] in lane 16i + 4b + j.
+// The block index b carries four disjoint column sets, summed across lanes at
+// the end, so no operand is replicated.  A wave owns 16 rows (four groups rho
+// of 4) x 16 samples (four groups gamma of 4); lane (i, b, k) takes row
+// 4 rho + i of X and sample 4 gamma + i of G in column slot sigma = 4b + k, i.e.
+// the W consecutive columns c0 + W sigma .. + W - 1 of each chunk of 16 W
+// columns; step t contracts column c0 + W sigma + t.  One step is 16 matrix
+// instructions (rho x gamma) on 4 + 4 operand registers.  Operands are widened
+// to FP64 (exact) and accumulated in FP64.  Block: four waves (64 rows) x 16
+// samples; KSPLIT groups of four waves take interleaved chunks and are summed
+// in a fixed order in LDS (deterministic).
+typedef float gf32x4 __attribute__((ext_vector_type(4)));
+typedef double gf64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short gu16x4 __attribute__((ext_vector_type(4)));
+#define TN_GLOBAL __attribute__((address_space(1)))
+
+// W consecutive values as loaded (16 B of FP32, 8 B of BF16, 16 B of FP64),
+// widened to FP64 only when used.
+template <typename T>
+struct RawW;
+template <>
+struct RawW<float> {
+  static constexpr int W = 4;
+  gf32x4 v;
+  __device__ __forceinline__ void load(const void *base, int64_t off) {
+    v = *((const TN_GLOBAL gf32x4 *)(reinterpret_cast<const float *>(base) + off));
+  }
+  __device__ __forceinline__ void set(int i, const void *base, int64_t off) {
+    v[i] = reinterpret_cast<const float *>(base)[off];
+  }
+  __device__ __forceinline__ double get(int i) const { return (double)v[i]; }
+};
+template <>
+struct RawW<double> {
+  static constexpr int W = 2;
+  gf64x2 v;
+  __device__ __forceinline__ void load(const void *base, int64_t off) {
+    v = *((const TN_GLOBAL gf64x2 *)(reinterpret_cast<const double *>(base) + off));
+  }
+  __device__ __forceinline__ void set(int i, const void *base, int64_t off) {
+    v[i] = reinterpret_cast<const double *>(base)[off];
+  }
+  __device__ __forceinline__ double get(int i) const { return v[i]; }
+};
+template <>
+struct RawW<uint16_t> {
+  static constexpr int W = 4;
+  gu16x4 v;
+  __device__ __forceinline__ void load(const void *base, int64_t off) {
+    v = *((const TN_GLOBAL gu16x4 *)(reinterpret_cast<const uint16_t *>(base) + off));
+  }
+  __device__ __forceinline__ void set(int i, const void *base, int64_t off) {
+    v[i] = reinterpret_cast<const uint16_t *>(base)[off];
+  }
+  __device__ __forceinline__ double get(int i) const { return (double)__uint_as_float((uint32_t)v[i] << 16); }
+};
+
+constexpr int kGemmRows = 64;     // rows per block (four waves of 16)
+constexpr int kGemmSamples = 16;  // samples per block
+
+template <typename T, typename A, int KSPLIT>
+__global__ __launch_bounds__(256 * KSPLIT) void m2_gemm_kernel(
     const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, const void *const *data,
     const A *__restrict__ gbuf, int64_t g_row, int64_t samples, A *__restrict__ wbuf,
     int64_t w_row, double *__restrict__ est, int64_t S, int64_t sample0) {
-  __shared__ A As[kTK][kTR + 4];
-  __shared__ A Bs[kTK][kTS + 4];
+  constexpr int W = RawW<T>::W;
+  static_assert(RawW<A>::W == W, "operand widths differ");
+  constexpr int32_t kChunk = 16 * W;
+  constexpr int32_t kStep = kChunk * KSPLIT;
+  __shared__ double red[KSPLIT > 1 ? (KSPLIT - 1) * 256 * 4 : 1];
   const M2Tile tl = tiles[blockIdx.x];
-  const M2Node nd = nodes[tl.node];
-  const int tid = threadIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.y * kTS;
-  const int tr = tid >> 4, ts = tid & 15;  // 16 x 16 threads, 4 x 4 outputs each
+  const M2Node &nd = nodes[tl.node];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rt = wave & 3, kg = wave >> 2;
+  const int lo = lane & 3, bq = (lane >> 2) & 3, kq = lane >> 4;
+  const int sigma = 4 * bq + kq;
+  const int64_t rows = nd.rows, after = nd.after;
+  const int32_t ncols = (int32_t)nd.ncols;  // below 2^31 (planner)
+  const int64_t row0 = (int64_t)tl.row0 + rt * 16 + lo;              // + 4 rho
+  const int64_t smp0 = (int64_t)blockIdx.y * kGemmSamples + lo;      // + 4 gamma
   const void *X = data[nd.tensor];
-  double accv[4][4];
+  bool row_ok[4], smp_ok[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) accv[i][j] = 0.0;
-
-  for (int64_t c0 = 0; c0 < nd.ncols; c0 += kTK) {
-    for (int i = tid; i < kTR * kTK; i += 256) {
-      const int r = i / kTK, k = i % kTK;
-      const int64_t row = tl.row0 + r, col = c0 + k;
-      A v = (A)0;
-      if (row < nd.rows && col < nd.ncols) {
-        const int64_t off = ((col / nd.after) * nd.rows + row) * nd.after + col % nd.after;
-        v = (A)load_val<T>(X, off);
-      }
-      As[k][r] = v;
-    }
-    for (int i = tid; i < kTS * kTK; i += 256) {
-      const int sl = i / kTK, k = i % kTK;
-      const int64_t smp = s0 + sl, col = c0 + k;
-      Bs[k][sl] = (smp < samples && col < nd.ncols) ? gbuf[smp * g_row + nd.g_off + col] : (A)0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = 0; k < kTK; ++k) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = (double)As[k][tr * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = (double)Bs[k][ts * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) accv[i][j] = fma(a[i], b[j], accv[i][j]);
-    }
-    __syncthreads();
+  for (int r = 0; r < 4; ++r) {
+    row_ok[r] = row0 + 4 * r < rows;
+    smp_ok[r] = smp0 + 4 * r < samples;
   }
+  const A *g0 = gbuf + (smp_ok[0] ? smp0 : 0) * g_row + nd.g_off;
+  const int64_t g4 = 4 * g_row;        // next sample group
+  const int64_t x4 = 4 * after;        // next row group
+  // W consecutive columns in one contiguous run of X, and alignment of X.
+  const bool vec = (after % W) == 0 &&
+                   (reinterpret_cast<uintptr_t>(X) & (uintptr_t)(W * sizeof(T) - 1)) == 0;
+  // Column c = c0 + W sigma of this lane; its X offset for row r is
+  // ((c / after) rows + r) after + c % after, tracked incrementally.
+  int32_t c = kg * kChunk + W * sigma;
+  const int32_t after32 = (int32_t)after;
+  int32_t qd = c / after32, rm = c - qd * after32;
+  const int32_t stepq = kStep / after32, stepr = kStep - stepq * after32;
+  auto load_chunk = [&](RawW<T> *xa, RawW<A> *gb) {
+    const int64_t xo = ((int64_t)qd * rows + row0) * after + rm;
+    if (vec && c + W - 1 < ncols) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t row = tl.row0 + tr * 4 + i;
-    if (row >= nd.rows) continue;
+      for (int r = 0; r < 4; ++r) {
+        if (row_ok[r]) xa[r].load(X, xo + r * x4);
+        else xa[r] = RawW<T>{};
+        if (smp_ok[r]) gb[r].load(g0 + r * g4, c);
+        else gb[r] = RawW<A>{};
+      }
+    } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t smp = s0 + ts * 4 + j;
-      if (smp >= samples) continue;
-      if (nd.root)
-        est[(int64_t)nd.net * S + sample0 + smp] = accv[i][j];
-      else
-        wbuf[smp * w_row + nd.w_off + row] = (A)accv[i][j];
+      for (int r = 0; r < 4; ++r) {
+        xa[r] = RawW<T>{};
+        gb[r] = RawW<A>{};
+      }
+#pragma unroll
+      for (int e = 0; e < W; ++e) {
+        const int32_t ce = c + e;
+        if (ce < ncols) {
+          const int32_t qe = ce / after32;
+          const int64_t xe = ((int64_t)qe * rows + row0) * after + (ce - qe * after32);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (row_ok[r]) xa[r].set(e, X, xe + r * x4);
+            if (smp_ok[r]) gb[r].set(e, g0 + r * g4, ce);
+          }
+        }
+      }
     }
+  };
+  auto next_chunk = [&]() {
+    c += kStep;
+    qd += stepq;
+    rm += stepr;
+    if (rm >= after32) { rm -= after32; ++qd; }
+  };
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[r][g] = 0.0;
+  // The trip count must be the same for all lanes of the wave (the matrix
+  // instruction works on the whole wave): loop over the chunk base, predicate
+  // the loads per lane.  Four or more waves per SIMD hide the load latency
+  // (holding the next chunk in registers as well costs occupancy and measured
+  // no faster).
+  RawW<T> xa[4];
+  RawW<A> gb[4];
+  for (int32_t cb = kg * kChunk; cb < ncols; cb += kStep) {
+    load_chunk(xa, gb);
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        av[r] = xa[r].get(t);
+        bv[r] = gb[r].get(t);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[r][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[r], bv[g], acc[r][g], 0, 0, 0);
+    }
+    next_chunk();
+  }
+  // Sum the four blocks (lane bits 2-3); every lane of a quadruple adds the
+  // same values in the same pairing, so all four hold the identical total.
+  // Lane (i, b, j) keeps row group rho = b: out[gamma] = D(row 4b + i, sample 4 gamma + j).
+  double out[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    double v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double x = acc[r][g];
+      x += __shfl_xor(x, 4, 64);
+      x += __shfl_xor(x, 8, 64);
+      v[r] = x;
+    }
+    out[g] = bq == 0 ? v[0] : bq == 1 ? v[1] : bq == 2 ? v[2] : v[3];
+  }
+  if constexpr (KSPLIT > 1) {
+    if (kg > 0) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) red[(((kg - 1) * 4 + rt) * 64 + lane) * 4 + g] = out[g];
+    }
+    __syncthreads();
+    if (kg > 0) return;
+#pragma unroll
+    for (int h = 1; h < KSPLIT; ++h)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) out[g] += red[(((h - 1) * 4 + rt) * 64 + lane) * 4 + g];
+  }
+  // D row of this lane: 4 b + i with i = lane / 16 (output layout), samples 4 gamma + (lane & 3)
+  const int64_t orow = (int64_t)tl.row0 + rt * 16 + 4 * bq + kq;
+  if (orow >= rows) return;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t smp = (int64_t)blockIdx.y * kGemmSamples + 4 * g + lo;
+    if (smp >= samples) continue;
+    if (nd.root)
+      est[(int64_t)nd.net * S + sample0 + smp] = out[g];
+    else
+      wbuf[smp * w_row + nd.w_off + orow] = (A)out[g];
   }
 }
 
@@ -390,11 +604,25 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
     if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
-    dim3 g2((unsigned)P->level_tiles[(size_t)d].size(), (unsigned)((n + kTS - 1) / kTS));
-    hipLaunchKernelGGL((m2_gemm_kernel<T, A>), g2, dim3(256), 0, st, P->d_nodes,
-                       P->d_level_tiles[(size_t)d], (const void *const *)p->d_data,
-                       reinterpret_cast<const A *>(P->d_g), P->g_row, n,
-                       reinterpret_cast<A *>(P->d_w), P->w_row, est, p->S, c0);
+    // Column split: enough waves for four per SIMD (256 CUs x 4), each group of
+    // four waves still taking at least 8 chunks of 32 columns.
+    dim3 g2((unsigned)P->level_tiles[(size_t)d].size(), (unsigned)((n + kGemmSamples - 1) / kGemmSamples));
+    const int64_t waves = 4ll * g2.x * g2.y;
+    int ks = 1;
+    while (ks < 4 && waves * ks < 4096 && P->level_maxcols[(size_t)d] >= 512ll * ks) ks *= 2;
+    const void *const *dp = (const void *const *)p->d_data;
+    const A *gb = reinterpret_cast<const A *>(P->d_g);
+    A *wb = reinterpret_cast<A *>(P->d_w);
+    const M2Tile *tl = P->d_level_tiles[(size_t)d];
+    if (ks == 1)
+      hipLaunchKernelGGL((m2_gemm_kernel<T, A, 1>), g2, dim3(256), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
+                         n, wb, P->w_row, est, p->S, c0);
+    else if (ks == 2)
+      hipLaunchKernelGGL((m2_gemm_kernel<T, A, 2>), g2, dim3(512), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
+                         n, wb, P->w_row, est, p->S, c0);
+    else
+      hipLaunchKernelGGL((m2_gemm_kernel<T, A, 4>), g2, dim3(1024), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
+                         n, wb, P->w_row, est, p->S, c0);
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
   }
@@ -513,6 +741,9 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
         nd.child_dim[i] = (int32_t)n.dims[u];
         nd.ncols *= n.dims[u];
         dsum += n.dims[u];
+        if (nd.ncols > 0x7fffffffll)
+          return set_error(TN_ERR_UNSUPPORTED,
+                           "acyclic method: network %d tensor %d: more than 2^31 child index tuples", j, k);
         const int e = c.edge_of[(size_t)u];
         nd.child_edge[i] = e;
         nd.child_tab[i] = edge_tab[(size_t)e];
@@ -597,14 +828,16 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   for (const M2Node &nd : P->h_nodes) maxd = std::max(maxd, nd.depth);
   P->level_nodes.assign((size_t)maxd + 1, {});
   P->level_tiles.assign((size_t)maxd + 1, {});
+  P->level_maxcols.assign((size_t)maxd + 1, 0);
   level_cols.assign((size_t)maxd + 1, 0);
   for (size_t i = 0; i < P->h_nodes.size(); ++i) {
     M2Node &nd = P->h_nodes[i];
     if (nd.nchild == 0) continue;
     nd.g_off = level_cols[(size_t)nd.depth];
-    level_cols[(size_t)nd.depth] += nd.ncols;
+    level_cols[(size_t)nd.depth] += (nd.ncols + 3) & ~3ll;  // 4-aligned rows of g
     P->level_nodes[(size_t)nd.depth].push_back((int32_t)i);
-    for (int r0 = 0; r0 < nd.rows; r0 += kTR) P->level_tiles[(size_t)nd.depth].push_back({(int32_t)i, r0});
+    P->level_maxcols[(size_t)nd.depth] = std::max(P->level_maxcols[(size_t)nd.depth], nd.ncols);
+    for (int r0 = 0; r0 < nd.rows; r0 += kGemmRows) P->level_tiles[(size_t)nd.depth].push_back({(int32_t)i, r0});
   }
   for (int64_t v : level_cols) P->g_row = std::max(P->g_row, v);
   if (P->g_row > 65535ll * 65536ll)
