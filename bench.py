@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6   # dense FP64 matrix cores (the same figure as FP64 vector)
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense BF16 matrix cores
 
 METRIC = "sketch estimates/s at 1e-2 rel. error; % HBM roofline; batched/learned vs plain"
 
@@ -47,6 +48,8 @@ def parse():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--batch", type=int, default=None)
+    ap.add_argument("--products", default="fp64", choices=["fp64", "bf16"],
+                    help="acyclic method: SMVP products on the FP64 (default) or BF16 matrix cores")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -164,6 +167,9 @@ def main():
         specs.append(T.NetworkSpec.from_network(n, ts))
     torch.cuda.synchronize()
     flags = T.TN_FLAG_PROFILE | (0 if os.environ.get("TN_SCATTER_SB") else T.TN_FLAG_AUTOTUNE)
+    bf16_products = a.products == "bf16" and method == "acyclic"
+    if bf16_products:
+        flags |= T.TN_FLAG_MFMA_BF16
     meth = T.TN_CYCLIC if method == "cyclic" else T.TN_ACYCLIC
     plan = T.Plan(specs, meth, m, S, 0, flags=flags)
     stats = torch.empty(2 * len(nets), dtype=torch.float64, device="cuda")
@@ -207,8 +213,9 @@ def main():
         flops_step = 2.0 * sum((n.nnz() - sum(int(np.prod(n.shape(k))) for k in range(n.p)
                                                if len(n.shape(k)) == 1 and k != 0)) for n in nets) * S
         achieved = flops_step / (sk_ms / a.steps * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None, "kernel": "m2_gemm_kernel",
+        peak = BF16_MFMA_PEAK_TFLOPS if bf16_products else FP64_MFMA_PEAK_TFLOPS
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "kernel": "m2_gemm_kernel",
                 "avg_launch_ms": avg_ms, "launches": sk_n, "flops_per_step": flops_step}
     st = stats.cpu().numpy().reshape(-1, 2)
     norms = np.array([n.input_norm() for n in nets])
@@ -231,6 +238,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "method": method, "networks": len(nets),
                    "samples_per_network": S, "m": m, "entries": entries,
+                   **({"products": "bf16 matrix cores, fp32 accumulation"} if bf16_products else {}),
                    "bytes_resident": entries * esize},
         "roofline": roof,
         "at_1e-2": {"median_input_relative_std": float(np.median(rel_std)),

@@ -81,6 +81,13 @@ extern "C" {
                                    samples-per-pass value on the bound data and keeps the
                                    fastest (that call synchronizes its stream); cached per
                                    plan shape for the life of the process */
+#define TN_FLAG_MFMA_BF16 0x8u  /* TN_ACYCLIC only: the SMVP products w_k = mat(X_k) G run on the
+                                   BF16 matrix cores (operands rounded to BF16 to nearest even,
+                                   FP32 accumulation) instead of the FP64 ones; the hashes,
+                                   sketches and combine are unchanged.  Rounding the operands
+                                   perturbs each w_k by about 2^-8 relative per tree level; the
+                                   estimate's error against exact arithmetic is measured and
+                                   stated by the tests (TN_ERR_UNSUPPORTED with TN_CYCLIC) */
 
 /* Kernel kinds for tn_plan_kernel_time. */
 #define TN_KERNEL_HASH 0        /* count-sketch table generation */

@@ -551,6 +551,135 @@ __global__ __launch_bounds__(256 * KSPLIT) void m2_gemm_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same product on the BF16 matrix cores (TN_FLAG_MFMA_BF16):
+// v_mfma_f32_16x16x32_bf16, lane layout (measured) A[i][k] in lane
+// i + 16 (k / 8) element k % 8, B[k][j] in lane j + 16 (k / 8) element k % 8,
+// D[i][j] in lane j + 16 (i / 4) item i % 4.  A wave owns 16 rows x 16 samples;
+// lane (i, q) supplies the 8 consecutive columns c0 + 8q .. + 7 of its X row and
+// of its G sample, rounded to BF16 to nearest even; accumulation in FP32.
+// Block and column split as for the FP64 kernel.
+typedef __bf16 gbf16x8 __attribute__((ext_vector_type(8)));
+typedef float gf32x4acc __attribute__((ext_vector_type(4)));
+
+// Eight consecutive values from `base + off` as FP32 (vector path: aligned and
+// in one contiguous run).
+template <typename T>
+__device__ __forceinline__ void load8(const void *base, int64_t off, float *v);
+template <>
+__device__ __forceinline__ void load8<float>(const void *base, int64_t off, float *v) {
+  const TN_GLOBAL gf32x4 *q = (const TN_GLOBAL gf32x4 *)(reinterpret_cast<const float *>(base) + off);
+  const gf32x4 a = q[0], b = q[1];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+template <>
+__device__ __forceinline__ void load8<double>(const void *base, int64_t off, float *v) {
+  const TN_GLOBAL gf64x2 *q = (const TN_GLOBAL gf64x2 *)(reinterpret_cast<const double *>(base) + off);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const gf64x2 a = q[i];
+    v[2 * i] = (float)a.x;
+    v[2 * i + 1] = (float)a.y;
+  }
+}
+template <>
+__device__ __forceinline__ void load8<uint16_t>(const void *base, int64_t off, float *v) {
+  const TN_GLOBAL gu16x4 *q = (const TN_GLOBAL gu16x4 *)(reinterpret_cast<const uint16_t *>(base) + off);
+  const gu16x4 a = q[0], b = q[1];
+  v[0] = __uint_as_float((uint32_t)a.x << 16); v[1] = __uint_as_float((uint32_t)a.y << 16);
+  v[2] = __uint_as_float((uint32_t)a.z << 16); v[3] = __uint_as_float((uint32_t)a.w << 16);
+  v[4] = __uint_as_float((uint32_t)b.x << 16); v[5] = __uint_as_float((uint32_t)b.y << 16);
+  v[6] = __uint_as_float((uint32_t)b.z << 16); v[7] = __uint_as_float((uint32_t)b.w << 16);
+}
+template <typename T>
+__device__ __forceinline__ float load1f(const void *base, int64_t off) {
+  return (float)load_val<T>(base, off);
+}
+
+template <typename T, typename A, int KSPLIT>
+__global__ __launch_bounds__(256 * KSPLIT) void m2_gemm_bf16_kernel(
+    const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, const void *const *data,
+    const A *__restrict__ gbuf, int64_t g_row, int64_t samples, A *__restrict__ wbuf,
+    int64_t w_row, double *__restrict__ est, int64_t S, int64_t sample0) {
+  constexpr int32_t kChunk = 32;
+  constexpr int32_t kStep = kChunk * KSPLIT;
+  __shared__ gf32x4acc red[KSPLIT > 1 ? (KSPLIT - 1) * 256 : 1];
+  const M2Tile tl = tiles[blockIdx.x];
+  const M2Node &nd = nodes[tl.node];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rt = wave & 3, kg = wave >> 2;
+  const int li = lane & 15, q = lane >> 4;
+  const int64_t rows = nd.rows, after = nd.after;
+  const int32_t ncols = (int32_t)nd.ncols;
+  const int64_t row = (int64_t)tl.row0 + rt * 16 + li;
+  const int64_t smp = (int64_t)blockIdx.y * kGemmSamples + li;
+  const bool row_ok = row < rows, smp_ok = smp < samples;
+  const void *X = data[nd.tensor];
+  const A *grow = gbuf + (smp_ok ? smp : 0) * g_row + nd.g_off;
+  // eight consecutive columns in one contiguous run, and alignment (rows of g
+  // start at multiples of 4 elements by construction)
+  const bool vec_x = (after % 8) == 0 &&
+                     (reinterpret_cast<uintptr_t>(X) & (uintptr_t)(4 * sizeof(T) - 1)) == 0;
+  const bool vec_g = ((nd.g_off | g_row) & 3) == 0;
+  int32_t c = kg * kChunk + 8 * q;
+  const int32_t after32 = (int32_t)after;
+  int32_t qd = c / after32, rm = c - qd * after32;
+  const int32_t stepq = kStep / after32, stepr = kStep - stepq * after32;
+  gf32x4acc acc = {0.f, 0.f, 0.f, 0.f};
+  for (int32_t cb = kg * kChunk; cb < ncols; cb += kStep) {
+    float xv[8], gv[8];
+    const bool full = c + 7 < ncols;
+    if (full && vec_x && row_ok) {
+      load8<T>(X, ((int64_t)qd * rows + row) * after + rm, xv);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int32_t ce = c + e;
+        float v = 0.f;
+        if (row_ok && ce < ncols) {
+          const int32_t qe = ce / after32;
+          v = load1f<T>(X, ((int64_t)qe * rows + row) * after + (ce - qe * after32));
+        }
+        xv[e] = v;
+      }
+    }
+    if (full && vec_g && smp_ok) {
+      load8<A>(grow, c, gv);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) gv[e] = (smp_ok && c + e < ncols) ? (float)grow[c + e] : 0.f;
+    }
+    gbf16x8 xa, gb;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      xa[e] = (__bf16)xv[e];
+      gb[e] = (__bf16)gv[e];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa, gb, acc, 0, 0, 0);
+    c += kStep;
+    qd += stepq;
+    rm += stepr;
+    if (rm >= after32) { rm -= after32; ++qd; }
+  }
+  if constexpr (KSPLIT > 1) {
+    if (kg > 0) red[(kg - 1) * 256 + rt * 64 + lane] = acc;
+    __syncthreads();
+    if (kg > 0) return;
+#pragma unroll
+    for (int h = 1; h < KSPLIT; ++h) acc += red[(h - 1) * 256 + rt * 64 + lane];
+  }
+  if (!smp_ok) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t orow = (int64_t)tl.row0 + rt * 16 + 4 * q + r;
+    if (orow >= rows) continue;
+    if (nd.root)
+      est[(int64_t)nd.net * S + sample0 + smp] = (double)acc[r];
+    else
+      wbuf[smp * w_row + nd.w_off + orow] = (A)acc[r];
+  }
+}
+
 // Export hook: x_k = C_{parent,k} w_k for non-root tensors (w_k = X_k for leaves).
 template <typename T, typename A>
 __global__ void m2_export_kernel(const M2Node *__restrict__ nodes, int32_t n_nodes,
@@ -614,15 +743,26 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     const A *gb = reinterpret_cast<const A *>(P->d_g);
     A *wb = reinterpret_cast<A *>(P->d_w);
     const M2Tile *tl = P->d_level_tiles[(size_t)d];
-    if (ks == 1)
+    if (p->flags & TN_FLAG_MFMA_BF16) {
+      if (ks == 1)
+        hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 1>), g2, dim3(256), 0, st, P->d_nodes, tl, dp, gb,
+                           P->g_row, n, wb, P->w_row, est, p->S, c0);
+      else if (ks == 2)
+        hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 2>), g2, dim3(512), 0, st, P->d_nodes, tl, dp, gb,
+                           P->g_row, n, wb, P->w_row, est, p->S, c0);
+      else
+        hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 4>), g2, dim3(1024), 0, st, P->d_nodes, tl, dp, gb,
+                           P->g_row, n, wb, P->w_row, est, p->S, c0);
+    } else if (ks == 1) {
       hipLaunchKernelGGL((m2_gemm_kernel<T, A, 1>), g2, dim3(256), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
                          n, wb, P->w_row, est, p->S, c0);
-    else if (ks == 2)
+    } else if (ks == 2) {
       hipLaunchKernelGGL((m2_gemm_kernel<T, A, 2>), g2, dim3(512), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
                          n, wb, P->w_row, est, p->S, c0);
-    else
+    } else {
       hipLaunchKernelGGL((m2_gemm_kernel<T, A, 4>), g2, dim3(1024), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
                          n, wb, P->w_row, est, p->S, c0);
+    }
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
   }
