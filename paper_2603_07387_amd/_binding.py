@@ -166,15 +166,18 @@ def _array(specs):
 
 
 def tn_sketch_plan(specs, method, m, samples, seed, root=-1, flags=0):
+    arr = specs if isinstance(specs, ctypes.Array) else _array(specs)
     handle = ctypes.c_void_p()
-    _check(load().tn_sketch_plan(_array(specs), len(specs), method, m, samples, seed, root, flags,
-                                 ctypes.byref(handle)))
+    _check(load().tn_sketch_plan(arr, len(arr), method, m, samples, seed, root, flags, ctypes.byref(handle)))
     return handle
 
 
 def tn_sketch_estimate(plan, specs, stream, stats, samples_out=None):
-    return _check(load().tn_sketch_estimate(plan, _array(specs), _stream(stream), _ptr(stats),
-                                            _ptr(samples_out)))
+    """`specs` is a list of NetworkSpec or an array built by _array() (reused
+    across calls: its structs point at each spec's data-pointer array, which
+    NetworkSpec.bind updates in place)."""
+    arr = specs if isinstance(specs, ctypes.Array) else _array(specs)
+    return _check(load().tn_sketch_estimate(plan, arr, _stream(stream), _ptr(stats), _ptr(samples_out)))
 
 
 def tn_contract_exact(spec, stream=None):
@@ -366,7 +369,8 @@ class Plan:
 
     def __init__(self, specs, method, m, samples, seed, root=-1, flags=0):
         self.specs = list(specs)
-        self.handle = tn_sketch_plan(self.specs, method, m, samples, seed, root, flags)
+        self._arr = _array(self.specs)   # marshalled once; rebinding data goes through the specs
+        self.handle = tn_sketch_plan(self._arr, method, m, samples, seed, root, flags)
         self.n_nets = len(self.specs)
         self.S = samples
         self.m = m
@@ -378,7 +382,7 @@ class Plan:
         dev = torch.device("cuda", torch.cuda.current_device())
         if stats is None:
             stats = torch.empty(2 * self.n_nets, dtype=torch.float64, device=dev)
-        tn_sketch_estimate(self.handle, self.specs, stream, stats, samples_out)
+        tn_sketch_estimate(self.handle, self._arr, stream, stats, samples_out)
         return stats
 
     def hashes(self, first=0, count=None, stream=None):
