@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--products", default="fp64", choices=["fp64", "bf16"],
                     help="acyclic method: SMVP products on the FP64 (default) or BF16 matrix cores")
+    ap.add_argument("--persistent", action="store_true",
+                    help="cyclic method: the persistent fused kernel (TN_FLAG_PERSISTENT)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -130,12 +132,19 @@ def cpu_baseline(workload, m, seconds):
                       f"{per} per process on {cores} processes, {wall:.1f} s wall"}
 
 
-def measured_traffic(workload_name, samples_per_pass, kernel_source):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    summary, if it was taken on this workload, schedule and kernel source."""
-    import glob
+def source_hash(kernel_sources):
     import hashlib
-    h = hashlib.sha256(open(os.path.join(ROOT, kernel_source), "rb").read()).hexdigest()[:16]
+    d = hashlib.sha256()
+    for src in kernel_sources:
+        d.update(open(os.path.join(ROOT, src), "rb").read())
+    return d.hexdigest()[:16]
+
+
+def measured_traffic(workload_name, samples_per_pass, kernel_sources):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, if it was taken on this workload, schedule and kernel sources."""
+    import glob
+    h = source_hash(kernel_sources)
     for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
         for line in open(path):
             if not line.startswith("machine-readable:"):
@@ -170,6 +179,9 @@ def main():
     bf16_products = a.products == "bf16" and method == "acyclic"
     if bf16_products:
         flags |= T.TN_FLAG_MFMA_BF16
+    persistent = a.persistent and method == "cyclic"
+    if persistent:
+        flags |= T.TN_FLAG_PERSISTENT
     meth = T.TN_CYCLIC if method == "cyclic" else T.TN_ACYCLIC
     plan = T.Plan(specs, meth, m, S, 0, flags=flags)
     stats = torch.empty(2 * len(nets), dtype=torch.float64, device="cuda")
@@ -195,17 +207,21 @@ def main():
         # Algorithmic bytes of one sketching launch: every tensor entry once per
         # pass of `sb` samples, the packed hash tables of each sample, the m-word
         # sketch of each (slot, sample).
-        sb, chunk = plan.query(8), plan.query(9)
+        # (The persistent kernel writes estimates only: no sketch vectors.)
+        sb, chunk, banks = plan.query(8), plan.query(9), plan.query(10)
         passes = -(-chunk // sb)
-        sketch_bytes = plan.query(6) * m * (8 if dtype == "float64" else 4)
+        sketch_bytes = 0 if persistent else plan.query(6) * m * (8 if dtype == "float64" else 4)
         launch_units = passes * entries * esize + chunk * plan.query(0) * 4 + chunk * sketch_bytes
         achieved = launch_units / (avg_ms * 1e-3) / 1e9
-        traffic, tsrc = measured_traffic(name, sb, "paper_2603_07387_amd/csrc/m1.hip")
+        kname = "m1_fused_kernel" if persistent else "m1_scatter_kernel"
+        src = ["paper_2603_07387_amd/csrc/fused.hip" if persistent else "paper_2603_07387_amd/csrc/m1.hip",
+               "paper_2603_07387_amd/csrc/m1_device.h"]
+        traffic, tsrc = measured_traffic(name, sb, src)
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": tsrc,
-                "kernel": "m1_scatter_kernel",
+                "kernel": kname,
                 "avg_launch_ms": avg_ms, "launches": sk_n, "algorithmic_bytes_per_launch": launch_units,
-                "samples_per_pass": sb}
+                "samples_per_pass": sb, "accumulator_banks": banks}
     else:
         # One GEMM launch per tree depth on the FP64 matrix cores: 2 * rows *
         # cols * samples flops of w_k = mat(X_k) G for every tensor with

@@ -88,6 +88,14 @@ extern "C" {
                                    perturbs each w_k by about 2^-8 relative per tree level; the
                                    estimate's error against exact arithmetic is measured and
                                    stated by the tests (TN_ERR_UNSUPPORTED with TN_CYCLIC) */
+#define TN_FLAG_PERSISTENT 0x10u /* TN_CYCLIC only: one persistent kernel per estimate call takes
+                                   (network, batch of samples) work items, largest first, from a
+                                   device queue, and for each scatters the tensors, transforms
+                                   and multiplies their sketches and writes the estimates, with
+                                   the sketches held in LDS throughout (64 <= m <= 4096; else
+                                   TN_ERR_UNSUPPORTED).  Same estimates as the two-kernel path
+                                   up to FP rounding of the combine (TN_ERR_UNSUPPORTED with
+                                   TN_ACYCLIC) */
 
 /* Kernel kinds for tn_plan_kernel_time. */
 #define TN_KERNEL_HASH 0        /* count-sketch table generation */
@@ -173,7 +181,10 @@ const char *tn_last_error(void);
  * sample), 1 = number of hash streams, 2 = S, 3 = m, 4 = n_nets,
  * 5 = total tensors, 6 = sketch-vector slots per sample
  * (one per tensor), 7 = method, 8 = samples sketched per pass over the data,
- * 9 = samples per launch (workspace chunk).
+ * 9 = samples per launch (workspace chunk), 10 = accumulator banks per sketch
+ * of the cyclic sketching pass (1 or 2; 0 for TN_ACYCLIC), 11 = 1 when the
+ * persistent kernel runs the plan (TN_FLAG_PERSISTENT).  Keys 8 and 10 may
+ * change after the first estimate of a TN_FLAG_AUTOTUNE plan.
  * Returns the value, or a negative code.
  */
 int64_t tn_plan_query(const tn_plan *plan, int32_t key);

@@ -18,93 +18,19 @@
 //                 Hermitian sum (1/m)(P_0 + P_{m/2} + 2 Re sum_{0<j<m/2} P_j)
 //                 gives the estimate.
 //   sample_stats: FP64 mean and unbiased variance over samples per network.
-#include "tn_internal.h"
+#include "m1_device.h"
 
 #include <hip/hip_bf16.h>
 
 namespace tn {
 namespace {
 
-template <typename T>
-__device__ __forceinline__ float to_acc(T v);
-template <>
-__device__ __forceinline__ float to_acc<float>(float v) { return v; }
-template <>
-__device__ __forceinline__ float to_acc<uint16_t>(uint16_t v) {
-  return __uint_as_float(((uint32_t)v) << 16);
-}
+using namespace m1dev;
 
-__device__ __forceinline__ double to_acc_any(double v) { return v; }
-__device__ __forceinline__ float to_acc_any(float v) { return v; }
-__device__ __forceinline__ float to_acc_any(uint16_t v) { return to_acc<uint16_t>(v); }
 
-// 16-byte vector of tensor entries (clang vector types, so they can be read
-// through a global-address-space pointer: global_load_dwordx4, not flat).
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
-template <typename T>
-struct Vec16;
-template <>
-struct Vec16<float> {
-  using type = f32x4;
-};
-template <>
-struct Vec16<double> {
-  using type = f64x2;
-};
-template <>
-struct Vec16<uint16_t> {
-  using type = u16x8;
-};
-
-// N consecutive packed column hashes from LDS (16-byte aligned for N >= 4,
-// 8-byte aligned for N = 2).
-template <int N>
-__device__ __forceinline__ void load_cols(const uint32_t *p, uint32_t *out);
-template <>
-__device__ __forceinline__ void load_cols<2>(const uint32_t *p, uint32_t *out) {
-  const uint2 t = *reinterpret_cast<const uint2 *>(p);
-  out[0] = t.x; out[1] = t.y;
-}
-template <>
-__device__ __forceinline__ void load_cols<4>(const uint32_t *p, uint32_t *out) {
-  const uint4 t = *reinterpret_cast<const uint4 *>(p);
-  out[0] = t.x; out[1] = t.y; out[2] = t.z; out[3] = t.w;
-}
-template <>
-__device__ __forceinline__ void load_cols<8>(const uint32_t *p, uint32_t *out) {
-  load_cols<4>(p, out);
-  load_cols<4>(p + 4, out + 4);
-}
-
-// Packed bucket/sign of a contiguous run of modes for one index: the sum of
-// the modes' buckets mod m and the product of their signs.
-__device__ __forceinline__ uint32_t combine_modes(const int32_t *__restrict__ tab,
-                                                  const ModeDesc *__restrict__ modes,
-                                                  int u_first, int u_last, uint32_t idx,
-                                                  uint32_t m, uint32_t mask) {
-  uint32_t acc = 0;
-  for (int u = u_last; u >= u_first; --u) {
-    const ModeDesc md = modes[u];
-    const uint32_t d = idx % (uint32_t)md.n;
-    idx /= (uint32_t)md.n;
-    const uint32_t v = (uint32_t)tab[md.table_off + d];
-    uint32_t h = v & ~kSignBit;
-    if (md.comp) h = (m - h) & mask;
-    acc = (((acc & ~kSignBit) + h) & mask) | ((acc ^ v) & kSignBit);
-  }
-  return acc;
-}
-
-// The sketches of one block are accumulated in 64-bit fixed point in LDS:
-// x -> round(x 2^scale) with ds_add_u64, which on gfx950 sustains about 16x the
-// rate of LDS float atomics, and makes every sketch independent of the order
-// of the atomic adds.  The block scale follows a running maximum of |x|:
-// scale = 62 - ceil(log2 N) - e with max|x| < 2^e, so N terms of the slot
-// cannot overflow; when a larger |x| appears the accumulators are shifted
-// right to the new scale before any further add.
-template <typename T, typename A, int SB>
+// One block streams one slot and accumulates the sketches of SB samples (see
+// scatter_slot), then writes them out as floating point.
+template <typename T, typename A, int SB, int BANKS>
 __global__ __launch_bounds__(256) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
@@ -116,238 +42,27 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
   const int64_t s0 = (int64_t)blockIdx.y * SB;
   const int nsb = (int)min((int64_t)SB, samples - s0);
   const uint32_t m = 1u << log2m, mask = m - 1;
-  const int L = sl.L, rows = sl.rows;
-
-  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);  // [SB][m]
-  uint32_t *colt = reinterpret_cast<uint32_t *>(smem + ((SB * m * 8 + 15) & ~15u));  // [SB][L]
-  uint32_t *rowt = colt + SB * L;                                         // [SB][rows]
-
-  for (int i = tid; i < SB * (int)m; i += 256) acc[i] = 0ull;
+  // BANKS banks of m words per sample (see scatter_slot), then the tables
+  const uint32_t signbit = BANKS == 2 ? sign_bank_offset(SB, m) : 0u;
+  const size_t acc_bytes = BANKS == 2 ? sign_bank_bytes(SB, m) : (size_t)SB * 8 * m;
+  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
+  uint32_t *colt = reinterpret_cast<uint32_t *>(smem + ((acc_bytes + 15) & ~(size_t)15));  // [SB][L]
+  uint32_t *rowt = colt + SB * sl.L;                                                     // [SB][rows]
+  for (int i = tid; i < (int)(acc_bytes / 8); i += 256) acc[i] = 0ull;
   if (tid < 2) s_max[tid] = 0ull;
-  // Packed tables hold the byte offset of the bucket (bucket * 8) and the sign
-  // bit, so a sum of a row and a column entry masked with 8(m - 1) is the LDS
-  // offset of the target accumulator.
-  auto to_offset = [](uint32_t v) { return ((v & ~kSignBit) << 3) | (v & kSignBit); };
-  for (int i = tid; i < nsb * L; i += 256) {
-    const int s = i / L, c = i - s * L;
-    colt[s * L + c] = to_offset(combine_modes(tables + (s0 + s) * W, modes, sl.mode0 + sl.split,
-                                              sl.mode0 + sl.q - 1, c, m, mask));
-  }
-  for (int i = tid; i < nsb * rows; i += 256) {
-    const int s = i / rows, r = i - s * rows;
-    rowt[s * rows + r] = to_offset(combine_modes(tables + (s0 + s) * W, modes, sl.mode0,
-                                                 sl.mode0 + sl.split - 1,
-                                                 (uint32_t)(sl.row0 + r), m, mask));
-  }
-  __syncthreads();
-  const uint32_t mask8 = mask << 3;
-  char *acc8 = reinterpret_cast<char *>(smem);
-
-  const T *X = reinterpret_cast<const T *>(data[sl.tensor]) + sl.row0 * (int64_t)L;
-  const uint32_t N = (uint32_t)rows * (uint32_t)L;
-  // Headroom: N terms below 2^(62 - lgN) each cannot overflow, and every
-  // scaled term stays below 2^51 so the magic-number conversion is exact.
-  const int lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
-  int scale = 0;       // accumulators hold x 2^scale
-  double sc = 1.0;     // 2^scale
-  double bound = 0.0;  // every |x| seen is < bound (0: none seen yet)
-  int par = 0;
-
-  // Block-wide running max of |x| (double-buffered so the read of one
-  // iteration cannot race with the next iteration's update), then a rescale
-  // when it reaches the bound.  Called by every thread once per iteration.
-  auto update_scale = [&](double lmax) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
-    if ((tid & 63) == 0) atomicMax(&s_max[par], (unsigned long long)__double_as_longlong(lmax));
-    __syncthreads();
-    const double bm = __longlong_as_double((long long)s_max[par]);
-    par ^= 1;
-    if (bm >= bound && bm > 0.0) {
-      int e;
-      (void)frexp(bm, &e);  // bm < 2^e
-      const int ns = 62 - lgN - e;
-      if (bound > 0.0 && scale > ns) {
-        const int d = scale - ns;
-        for (int i = tid; i < SB * (int)m; i += 256)
-          acc[i] = (unsigned long long)((long long)acc[i] >> d);
-        __syncthreads();
-      }
-      scale = ns;
-      sc = ldexp(1.0, ns);
-      bound = ldexp(1.0, e);
-    }
-  };
-  // round(x 2^scale) for |x 2^scale| < 2^51: adding 1.5 2^52 leaves the
-  // rounded integer in the low mantissa bits.
-  auto to_fixed = [&](double x) -> long long {
-    const double kMagic = 6755399441055744.0;
-    return __double_as_longlong(fma(x, sc, kMagic)) - __double_as_longlong(kMagic);
-  };
-  // One fixed-point add: the sample's accumulator block starts at s * 8m bytes
-  // and the masked offset sum stays inside it.
-  auto add_fixed = [&](int s, uint32_t hv, uint32_t lv, long long v) {
-    const uint32_t a = ((hv + lv) & mask8) | ((uint32_t)s * (m << 3));
-    atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + a),
-              (unsigned long long)(((hv ^ lv) & kSignBit) ? -v : v));
-  };
-  // Add entry x (row r, column c) to the sketch of every sample of the batch.
-  auto scatter_one = [&](double x, uint32_t r, uint32_t c) {
-    const long long v = to_fixed(x);
-    uint32_t hv[SB], lv[SB];
-#pragma unroll
-    for (int s = 0; s < SB; ++s) { hv[s] = rowt[s * rows + r]; lv[s] = colt[s * L + c]; }
-#pragma unroll
-    for (int s = 0; s < SB; ++s)
-      if (s < nsb) add_fixed(s, hv[s], lv[s], v);
-  };
-  constexpr int VEC = 16 / (int)sizeof(T);   // entries per 16-byte load
-  // Row and column entries of every sample for VEC consecutive entries of one
-  // row (all reads issued before any add, so one LDS wait covers them).
-  auto read_tabs = [&](uint32_t r, uint32_t c, uint32_t *hv, uint32_t (*lv)[VEC]) {
-#pragma unroll
-    for (int s = 0; s < SB; ++s) {
-      hv[s] = rowt[s * rows + r];
-      load_cols<VEC>(colt + s * L + c, lv[s]);
-    }
-  };
-  constexpr int UNROLL = 4;                  // 16-byte loads in flight per thread
-  const bool vec = (L % VEC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
-  if (vec) {
-    // Rows are multiples of VEC long and the slot starts 16-byte aligned, so
-    // the VEC entries of one load share a row.
-    using V = typename Vec16<T>::type;
-    const V __attribute__((address_space(1))) *Xv =
-        (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X);
-    const uint32_t NV = N / VEC;
-    for (uint32_t v0 = 0; v0 < NV; v0 += 256 * UNROLL) {
-      // Unconditional loads (index clamped into the slot) keep all UNROLL loads
-      // in flight; out-of-range lanes are masked when the values are used.
-      V buf[UNROLL];
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) buf[u] = Xv[min(v0 + u * 256 + tid, NV - 1)];
-      double lmax = 0.0;
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const T *xs = reinterpret_cast<const T *>(&buf[u]);
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
-      }
-      update_scale(lmax);
-      uint32_t rr[UNROLL], cc[UNROLL];
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const uint32_t e = min(v0 + u * 256 + tid, NV - 1) * VEC;  // clamped: valid table reads
-        rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
-        cc[u] = e - rr[u] * (uint32_t)L;
-      }
-      // Software pipeline: the table reads of vector u + 1 are issued before the
-      // adds of vector u.
-      uint32_t hv[2][SB], lv[2][SB][VEC];
-      read_tabs(rr[0], cc[0], hv[0], lv[0]);
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
-        if (v0 + u * 256 + tid < NV) {
-          const T *xs = reinterpret_cast<const T *>(&buf[u]);
-          long long q[VEC];
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) q[i] = to_fixed((double)to_acc_any(xs[i]));
-#pragma unroll
-          for (int s = 0; s < SB; ++s)
-            if (s < nsb) {
-#pragma unroll
-              for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i]);
-            }
-        }
-      }
-    }
-  } else {
-    const T __attribute__((address_space(1))) *Xg =
-        (const T __attribute__((address_space(1))) *)X;
-    for (uint32_t e0 = 0; e0 < N; e0 += 256 * UNROLL) {
-      T buf[UNROLL];
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) buf[u] = Xg[min(e0 + u * 256 + tid, N - 1)];
-      double lmax = 0.0;
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) lmax = fmax(lmax, fabs((double)to_acc_any(buf[u])));
-      update_scale(lmax);
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const uint32_t e = e0 + u * 256 + tid;
-        if (e < N) {
-          const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
-          scatter_one((double)to_acc_any(buf[u]), r, e - r * (uint32_t)L);
-        }
-      }
-    }
-  }
-  __syncthreads();
-
+  const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
+  FixedScale fs;
+  fs.lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
+  scatter_slot<T, SB, BANKS>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * m, signbit, colt,
+                             rowt, s_max, fs);
+  const unsigned long long *neg = acc + signbit / 8;
   for (int i = tid; i < nsb * (int)m; i += 256) {
     const int s = i >> log2m;
     const int b = i & mask;
-    ybuf[((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + b] =
-        (A)ldexp((double)(long long)acc[i], -scale);
+    // positive bank minus negative bank
+    const long long v = BANKS == 2 ? (long long)(acc[i] - neg[i]) : (long long)acc[i];
+    ybuf[((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + b] = (A)ldexp((double)v, -fs.scale);
   }
-}
-
-template <typename A>
-struct Cplx;
-template <>
-struct Cplx<float> {
-  using type = float2;
-};
-template <>
-struct Cplx<double> {
-  using type = double2;
-};
-
-// In-place radix-2 decimation-in-time FFT of M points held in LDS in
-// bit-reversed order; natural-order output.  F[j][b] = exp(-2 pi i j b / M).
-template <typename A, int LOG2M>
-__device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
-                                        const typename Cplx<A>::type *__restrict__ tw) {
-  constexpr int M = 1 << LOG2M;
-  using A2 = typename Cplx<A>::type;
-#pragma unroll 1
-  for (int lg = 1; lg <= LOG2M; ++lg) {
-    const int half = 1 << (lg - 1);
-    for (int q = threadIdx.x; q < M / 2; q += 256) {
-      const int k = q & (half - 1);
-      const int a = ((q >> (lg - 1)) << lg) + k;
-      const int b = a + half;
-      const A2 w = tw[k << (LOG2M - lg)];
-      const A2 za = z[a], zb = z[b];
-      const A tr = w.x * zb.x - w.y * zb.y;
-      const A ti = w.x * zb.y + w.y * zb.x;
-      z[a] = A2{za.x + tr, za.y + ti};
-      z[b] = A2{za.x - tr, za.y - ti};
-    }
-    __syncthreads();
-  }
-}
-
-template <int LOG2M>
-__device__ __forceinline__ int bitrev(int b) {
-  if constexpr (LOG2M == 0) {
-    return 0;
-  } else {
-    return (int)(__brev((unsigned)b) >> (32 - LOG2M));
-  }
-}
-
-__device__ __forceinline__ double block_sum_256(double v, double *red) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) red[wv] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) t = red[0] + red[1] + red[2] + red[3];
-  __syncthreads();
-  return t;
 }
 
 template <typename A, int LOG2M>
@@ -467,7 +182,7 @@ __global__ void twiddle_kernel(int64_t m, typename Cplx<A>::type *out) {
 
 template <typename T, typename A, int SB>
 int scatter_sb(const M1Launch &L, hipStream_t st) {
-  auto kern = m1_scatter_kernel<T, A, SB>;
+  auto kern = L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2> : m1_scatter_kernel<T, A, SB, 1>;
   if (L.lds_bytes > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)L.lds_bytes));

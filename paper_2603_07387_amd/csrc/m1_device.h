@@ -1,0 +1,355 @@
+// Device code shared by the cyclic method's kernels (m1.hip, fused.hip):
+// element conversions, vector types, the packed mode hashes, the fixed-point
+// slot scatter and the LDS FFT.
+#pragma once
+
+#include "tn_internal.h"
+
+namespace tn {
+namespace m1dev {
+
+template <typename T>
+__device__ __forceinline__ float to_acc(T v);
+template <>
+__device__ __forceinline__ float to_acc<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_acc<uint16_t>(uint16_t v) {
+  return __uint_as_float(((uint32_t)v) << 16);
+}
+
+__device__ __forceinline__ double to_acc_any(double v) { return v; }
+__device__ __forceinline__ float to_acc_any(float v) { return v; }
+__device__ __forceinline__ float to_acc_any(uint16_t v) { return to_acc<uint16_t>(v); }
+
+// 16-byte vector of tensor entries (clang vector types, so they can be read
+// through a global-address-space pointer: global_load_dwordx4, not flat).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = f32x4;
+};
+template <>
+struct Vec16<double> {
+  using type = f64x2;
+};
+template <>
+struct Vec16<uint16_t> {
+  using type = u16x8;
+};
+
+// N consecutive packed column hashes from LDS (16-byte aligned for N >= 4,
+// 8-byte aligned for N = 2).
+template <int N>
+__device__ __forceinline__ void load_cols(const uint32_t *p, uint32_t *out);
+template <>
+__device__ __forceinline__ void load_cols<2>(const uint32_t *p, uint32_t *out) {
+  const uint2 t = *reinterpret_cast<const uint2 *>(p);
+  out[0] = t.x; out[1] = t.y;
+}
+template <>
+__device__ __forceinline__ void load_cols<4>(const uint32_t *p, uint32_t *out) {
+  const uint4 t = *reinterpret_cast<const uint4 *>(p);
+  out[0] = t.x; out[1] = t.y; out[2] = t.z; out[3] = t.w;
+}
+template <>
+__device__ __forceinline__ void load_cols<8>(const uint32_t *p, uint32_t *out) {
+  load_cols<4>(p, out);
+  load_cols<4>(p + 4, out + 4);
+}
+
+// Packed bucket/sign of a contiguous run of modes for one index: the sum of
+// the modes' buckets mod m and the product of their signs.
+__device__ __forceinline__ uint32_t combine_modes(const int32_t *__restrict__ tab,
+                                                  const ModeDesc *__restrict__ modes,
+                                                  int u_first, int u_last, uint32_t idx,
+                                                  uint32_t m, uint32_t mask) {
+  uint32_t acc = 0;
+  for (int u = u_last; u >= u_first; --u) {
+    const ModeDesc md = modes[u];
+    const uint32_t d = idx % (uint32_t)md.n;
+    idx /= (uint32_t)md.n;
+    const uint32_t v = (uint32_t)tab[md.table_off + d];
+    uint32_t h = v & ~kSignBit;
+    if (md.comp) h = (m - h) & mask;
+    acc = (((acc & ~kSignBit) + h) & mask) | ((acc ^ v) & kSignBit);
+  }
+  return acc;
+}
+
+// Fixed-point state of one set of sketch accumulators.  The sketches are
+// accumulated in 64-bit fixed point in LDS: x -> round(x 2^scale) with
+// ds_add_u64, which on gfx950 sustains about 16x the rate of LDS float atomics
+// and makes every sketch independent of the order of the atomic adds.  The
+// scale follows a running maximum of |x|: scale = 62 - lgN - e with
+// max|x| < 2^e, where 2^lgN bounds the number of terms the set receives, so
+// they cannot overflow; when a larger |x| appears the accumulators are shifted
+// right to the new scale before any further add.
+struct FixedScale {
+  int scale = 0;       // accumulators hold x 2^scale
+  double sc = 1.0;     // 2^scale
+  double bound = 0.0;  // every |x| seen is < bound (0: none seen yet)
+  int lgN = 11;        // >= ceil(log2(terms)) and >= 11
+  int par = 0;         // parity of the double-buffered running maximum
+};
+
+// Layout of SB two-bank sketches of m words: positive banks of the SB samples
+// back to back, the negative banks `signbit` bytes after them.
+__host__ __device__ constexpr uint32_t sign_bank_offset(int sb, uint32_t m) {
+  return 8u * m * (sb <= 2 ? 2u : sb <= 4 ? 4u : sb <= 8 ? 8u : 16u);
+}
+__host__ __device__ constexpr size_t sign_bank_bytes(int sb, uint32_t m) {
+  return (size_t)sign_bank_offset(sb, m) + (size_t)sb * 8u * m;
+}
+
+// Scatter one slot (a run of rows of one tensor) into the fixed-point
+// sketches of nsb samples.  With BANKS = 1 a sketch is one bank of m words
+// and a term of sign -1 is negated before its add (sample s's bank at byte
+// s * sbytes; signbit unused).  With BANKS = 2 each sketch is a pair of banks of m words: terms
+// of sign +1 go to the positive bank, terms of sign -1 to the negative one,
+// and the sketch is their difference.  Sample s's positive bank starts at byte
+// s * sbytes from acc, its negative bank `signbit` bytes further; signbit is a
+// power of two of at least 16 m.  The packed tables hold bucket * 8 plus
+// signbit for sign -1, so the sum of a row and a column entry has the product
+// of the two signs in the signbit position (the bucket sum stays below 16 m),
+// and masking it with 8(m - 1) | signbit leaves the byte offset of the target
+// word: no sign test and no negation per term.
+// Builds the slot's packed row and column tables in rowt / colt (LDS, SB x
+// rows and SB x L words), then streams the slot once from HBM with 16-byte
+// loads.  s_max (2 words of LDS) holds the running maximum; both it and fs
+// carry over between calls that feed the same sketches.  Every thread of the
+// block calls it; it starts and ends with a barrier.
+template <typename T, int SB, int BANKS>
+__device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDesc *__restrict__ modes,
+                                             const void *const *__restrict__ data,
+                                             const int32_t *__restrict__ tables, int64_t W, int nsb,
+                                             int log2m, unsigned long long *acc, uint32_t sbytes,
+                                             uint32_t signbit, uint32_t *colt, uint32_t *rowt,
+                                             unsigned long long *s_max, FixedScale &fs) {
+  const int tid = threadIdx.x;
+  const uint32_t m = 1u << log2m, mask = m - 1;
+  const int L = sl.L, rows = sl.rows;
+  auto to_offset = [signbit](uint32_t v) {
+    if constexpr (BANKS == 2) return ((v & ~kSignBit) << 3) + ((v & kSignBit) ? signbit : 0u);
+    else return ((v & ~kSignBit) << 3) | (v & kSignBit);  // sign stays in bit 31
+  };
+  __syncthreads();  // earlier readers of the tables are done
+  for (int i = tid; i < nsb * L; i += 256) {
+    const int s = i / L, c = i - s * L;
+    colt[s * L + c] = to_offset(combine_modes(tables + s * W, modes, sl.mode0 + sl.split,
+                                              sl.mode0 + sl.q - 1, c, m, mask));
+  }
+  for (int i = tid; i < nsb * rows; i += 256) {
+    const int s = i / rows, r = i - s * rows;
+    rowt[s * rows + r] = to_offset(combine_modes(tables + s * W, modes, sl.mode0,
+                                                 sl.mode0 + sl.split - 1,
+                                                 (uint32_t)(sl.row0 + r), m, mask));
+  }
+  __syncthreads();
+  const uint32_t amask = (mask << 3) | (BANKS == 2 ? signbit : 0u);
+  char *acc8 = reinterpret_cast<char *>(acc);
+  const T *X = reinterpret_cast<const T *>(data[sl.tensor]) + sl.row0 * (int64_t)L;
+  const uint32_t N = (uint32_t)rows * (uint32_t)L;
+
+  // Block-wide running max of |x| (double-buffered so the read of one
+  // iteration cannot race with the next iteration's update), then a rescale
+  // when it reaches the bound.  Called by every thread once per iteration.
+  auto update_scale = [&](double lmax) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
+    if ((tid & 63) == 0) atomicMax(&s_max[fs.par], (unsigned long long)__double_as_longlong(lmax));
+    __syncthreads();
+    const double bm = __longlong_as_double((long long)s_max[fs.par]);
+    fs.par ^= 1;
+    if (bm >= fs.bound && bm > 0.0) {
+      int e;
+      (void)frexp(bm, &e);  // bm < 2^e
+      const int ns = 62 - fs.lgN - e;
+      if (fs.bound > 0.0 && fs.scale > ns) {
+        const int d = fs.scale - ns;
+        for (int i = tid; i < BANKS * nsb * (int)m; i += 256) {
+          const int si = BANKS == 2 ? i >> (log2m + 1) : i >> log2m;
+          const int bank = BANKS == 2 ? (i >> log2m) & 1 : 0, b = i & (int)mask;
+          unsigned long long *w = reinterpret_cast<unsigned long long *>(
+              reinterpret_cast<char *>(acc) + (size_t)si * sbytes + (bank ? signbit : 0u)) + b;
+          *w = (unsigned long long)((long long)*w >> d);
+        }
+        __syncthreads();
+      }
+      fs.scale = ns;
+      fs.sc = ldexp(1.0, ns);
+      fs.bound = ldexp(1.0, e);
+    }
+  };
+  // round(x 2^scale) for |x 2^scale| < 2^51: adding 1.5 2^52 leaves the
+  // rounded integer in the low mantissa bits.
+  auto to_fixed = [&](double x) -> long long {
+    const double kMagic = 6755399441055744.0;
+    return __double_as_longlong(fma(x, fs.sc, kMagic)) - __double_as_longlong(kMagic);
+  };
+  // One fixed-point add into sample s's sketch (its sign selects the bank).
+  auto add_fixed = [&](int s, uint32_t hv, uint32_t lv, long long v) {
+    const uint32_t a = ((hv + lv) & amask) + (uint32_t)s * sbytes;
+    if constexpr (BANKS == 2)
+      atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + a), (unsigned long long)v);
+    else
+      atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + a),
+                (unsigned long long)(((hv ^ lv) & kSignBit) ? -v : v));
+  };
+  // Add entry x (row r, column c) to the sketch of every sample of the batch.
+  auto scatter_one = [&](double x, uint32_t r, uint32_t c) {
+    const long long v = to_fixed(x);
+    uint32_t hv[SB], lv[SB];
+#pragma unroll
+    for (int s = 0; s < SB; ++s) { hv[s] = rowt[s * rows + r]; lv[s] = colt[s * L + c]; }
+#pragma unroll
+    for (int s = 0; s < SB; ++s)
+      if (s < nsb) add_fixed(s, hv[s], lv[s], v);
+  };
+  constexpr int VEC = 16 / (int)sizeof(T);   // entries per 16-byte load
+  // Row and column entries of every sample for VEC consecutive entries of one
+  // row (all reads issued before any add, so one LDS wait covers them).
+  auto read_tabs = [&](uint32_t r, uint32_t c, uint32_t *hv, uint32_t (*lv)[VEC]) {
+#pragma unroll
+    for (int s = 0; s < SB; ++s) {
+      hv[s] = rowt[s * rows + r];
+      load_cols<VEC>(colt + s * L + c, lv[s]);
+    }
+  };
+  constexpr int UNROLL = 4;                  // 16-byte loads in flight per thread
+  const bool vec = (L % VEC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  if (vec) {
+    // Rows are multiples of VEC long and the slot starts 16-byte aligned, so
+    // the VEC entries of one load share a row.
+    using V = typename Vec16<T>::type;
+    const V __attribute__((address_space(1))) *Xv =
+        (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X);
+    const uint32_t NV = N / VEC;
+    for (uint32_t v0 = 0; v0 < NV; v0 += 256 * UNROLL) {
+      // Unconditional loads (index clamped into the slot) keep all UNROLL loads
+      // in flight; out-of-range lanes are masked when the values are used.
+      V buf[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) buf[u] = Xv[min(v0 + u * 256 + tid, NV - 1)];
+      double lmax = 0.0;
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const T *xs = reinterpret_cast<const T *>(&buf[u]);
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+      }
+      update_scale(lmax);
+      uint32_t rr[UNROLL], cc[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const uint32_t e = min(v0 + u * 256 + tid, NV - 1) * VEC;  // clamped: valid table reads
+        rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
+        cc[u] = e - rr[u] * (uint32_t)L;
+      }
+      // Software pipeline: the table reads of vector u + 1 are issued before the
+      // adds of vector u.
+      uint32_t hv[2][SB], lv[2][SB][VEC];
+      read_tabs(rr[0], cc[0], hv[0], lv[0]);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
+        if (v0 + u * 256 + tid < NV) {
+          const T *xs = reinterpret_cast<const T *>(&buf[u]);
+          long long q[VEC];
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) q[i] = to_fixed((double)to_acc_any(xs[i]));
+#pragma unroll
+          for (int s = 0; s < SB; ++s)
+            if (s < nsb) {
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i]);
+            }
+        }
+      }
+    }
+  } else {
+    const T __attribute__((address_space(1))) *Xg =
+        (const T __attribute__((address_space(1))) *)X;
+    for (uint32_t e0 = 0; e0 < N; e0 += 256 * UNROLL) {
+      T buf[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) buf[u] = Xg[min(e0 + u * 256 + tid, N - 1)];
+      double lmax = 0.0;
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) lmax = fmax(lmax, fabs((double)to_acc_any(buf[u])));
+      update_scale(lmax);
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const uint32_t e = e0 + u * 256 + tid;
+        if (e < N) {
+          const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
+          scatter_one((double)to_acc_any(buf[u]), r, e - r * (uint32_t)L);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename A>
+struct Cplx;
+template <>
+struct Cplx<float> {
+  using type = float2;
+};
+template <>
+struct Cplx<double> {
+  using type = double2;
+};
+
+// In-place radix-2 decimation-in-time FFT of M points held in LDS in
+// bit-reversed order; natural-order output.  F[j][b] = exp(-2 pi i j b / M).
+template <typename A, int LOG2M>
+__device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
+                                        const typename Cplx<A>::type *__restrict__ tw) {
+  constexpr int M = 1 << LOG2M;
+  using A2 = typename Cplx<A>::type;
+#pragma unroll 1
+  for (int lg = 1; lg <= LOG2M; ++lg) {
+    const int half = 1 << (lg - 1);
+    for (int q = threadIdx.x; q < M / 2; q += 256) {
+      const int k = q & (half - 1);
+      const int a = ((q >> (lg - 1)) << lg) + k;
+      const int b = a + half;
+      const A2 w = tw[k << (LOG2M - lg)];
+      const A2 za = z[a], zb = z[b];
+      const A tr = w.x * zb.x - w.y * zb.y;
+      const A ti = w.x * zb.y + w.y * zb.x;
+      z[a] = A2{za.x + tr, za.y + ti};
+      z[b] = A2{za.x - tr, za.y - ti};
+    }
+    __syncthreads();
+  }
+}
+
+template <int LOG2M>
+__device__ __forceinline__ int bitrev(int b) {
+  if constexpr (LOG2M == 0) {
+    return 0;
+  } else {
+    return (int)(__brev((unsigned)b) >> (32 - LOG2M));
+  }
+}
+
+__device__ __forceinline__ double block_sum_256(double v, double *red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return t;
+}
+
+}  // namespace m1dev
+}  // namespace tn

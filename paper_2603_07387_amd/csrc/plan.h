@@ -71,11 +71,26 @@ struct tn_plan {
   void *d_tw = nullptr;
   void *d_ybuf = nullptr;
   int sb = 1;
+  int banks = 1;            // scatter accumulator banks (autotuned: 1 or 2)
   size_t scatter_lds = 0;
   int64_t chunk = 0;        // samples per workspace pass
   int64_t chunk_alloc = 0;  // samples the workspace was sized for
   size_t worst_cols_rows = 0;
   bool tuned = false;
+
+  // persistent fused kernel (TN_FLAG_PERSISTENT)
+  bool fused = false;
+  int fused_sb = 1;
+  int fused_banks = 1;
+  size_t fused_lds = 0;
+  int64_t fused_chunk = 0;
+  int64_t fused_chunk_cap = 0;       // samples per launch before rounding to fused_sb
+  std::vector<int64_t> net_work;     // per network: entries + pair-FFT work
+  int64_t fused_blocks = 0;
+  int32_t n_items = 0;
+  tn::FusedItem *d_items = nullptr;
+  int32_t *d_counter = nullptr;
+  int32_t *d_tensor_lgn = nullptr;
 
   // per-sample estimates [n_nets][S]
   double *d_est = nullptr;

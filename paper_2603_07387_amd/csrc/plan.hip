@@ -11,6 +11,7 @@
 #include <cstdlib>
 
 #include "plan.h"
+#include "m1_device.h"
 
 namespace tn {
 namespace {
@@ -41,6 +42,49 @@ int upload(T **ptr, const std::vector<T> &v) {
 }
 
 size_t acc_size(int dtype) { return dtype == TN_F64 ? sizeof(double) : sizeof(float); }
+
+// LDS of one scatter block: the fixed-point accumulators (p->banks banks of m
+// 8-byte words per sample) plus the packed tables.  (+64: the accumulator
+// block is padded to 16 bytes and the kernel keeps a 16-byte running maximum
+// in static LDS.)
+size_t scatter_lds_for(const tn_plan *p, int sb) {
+  const size_t acc = p->banks == 2 ? m1dev::sign_bank_bytes(sb, (uint32_t)p->m) : (size_t)sb * 8 * p->m;
+  return acc + (size_t)sb * 4 * p->worst_cols_rows + 64;
+}
+
+constexpr size_t kFusedStatic = 128;  // static LDS of the persistent kernel
+
+// Configure the persistent kernel for `sb` samples per item and `banks`
+// accumulator banks: LDS, chunk (a multiple of sb), the work items of one
+// chunk sorted by decreasing network work, and the grid (CUs x blocks per CU).
+int fused_configure(tn_plan *p, int sb, int banks) {
+  const size_t lds = m1_fused_lds(sb, banks, p->m, (int32_t)p->worst_cols_rows);
+  if (lds + kFusedStatic > p->max_lds)
+    return set_error(TN_ERR_UNSUPPORTED, "persistent kernel needs %zu bytes of LDS", lds + kFusedStatic);
+  int64_t fc = p->fused_chunk_cap;
+  if (fc > sb) fc = fc / sb * sb;
+  std::vector<FusedItem> items;
+  for (int j = 0; j < p->n_nets; ++j)
+    for (int64_t s0 = 0; s0 < fc; s0 += sb) items.push_back(FusedItem{j, (int32_t)s0});
+  std::stable_sort(items.begin(), items.end(), [&](const FusedItem &a, const FusedItem &b) {
+    return p->net_work[(size_t)a.net] > p->net_work[(size_t)b.net];
+  });
+  if (items.size() > 0x7fffffff) return set_error(TN_ERR_UNSUPPORTED, "persistent kernel: too many items");
+  if (p->d_items) (void)hipFree(p->d_items);
+  p->d_items = nullptr;
+  int rc = upload(&p->d_items, items);
+  if (rc != TN_OK) return rc;
+  int cus = 0;
+  TN_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)(160 * 1024) / (int64_t)(lds + kFusedStatic)));
+  p->fused_sb = sb;
+  p->fused_banks = banks;
+  p->fused_lds = lds;
+  p->fused_chunk = fc;
+  p->n_items = (int32_t)items.size();
+  p->fused_blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)items.size(), (int64_t)cus * per_cu));
+  return TN_OK;
+}
 
 int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &chk) {
   const size_t as = acc_size(p->dtype);
@@ -114,10 +158,14 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   size_t worst_cols_rows = 0;
   for (const ScatterSlot &sl : p->h_slots)
     worst_cols_rows = std::max(worst_cols_rows, (size_t)(sl.L + sl.rows));
-  // 64-bit fixed-point accumulators (8 bytes per bucket) plus packed tables.
-  // (+64: the accumulator block is padded to 16 bytes and the kernel keeps a
-  // 16-byte running maximum in static LDS.)
-  auto lds_for = [&](int sb) { return (size_t)sb * ((size_t)p->m * 8 + 4 * worst_cols_rows) + 64; };
+  // 64-bit fixed-point accumulators (two banks of 8-byte words per sample)
+  // plus packed tables.  (+64: the accumulator block is padded to 16 bytes and
+  // the kernel keeps a 16-byte running maximum in static LDS.)
+  // One bank with signed adds by default; TN_FLAG_AUTOTUNE also times two
+  // banks (the sign in the address: fewer ALU operations, twice the LDS).
+  p->worst_cols_rows = worst_cols_rows;
+  p->banks = 1;
+  auto lds_for = [&](int sb) { return scatter_lds_for(p, sb); };
   p->sb = 1;
   for (int sb : {8, 4, 2}) {
     if (sb <= p->S && lds_for(sb) <= 81920) { p->sb = sb; break; }
@@ -138,6 +186,42 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   p->chunk_alloc = chunk;
   if (chunk > 16) chunk = chunk / 16 * 16;  // a multiple of every samples-per-pass choice
   p->chunk = chunk;
+  int64_t table_samples = chunk;
+
+  // Persistent fused kernel: per-tensor headroom, per-network work (items are
+  // handed out largest first), then a default configuration (one bank, as
+  // many samples per item as fit 80 KB of LDS); TN_FLAG_AUTOTUNE may retune.
+  if (p->flags & TN_FLAG_PERSISTENT) {
+    if (p->log2m < 6 || p->log2m > 12)
+      return set_error(TN_ERR_UNSUPPORTED, "persistent kernel: m = %lld outside 64..4096", (long long)p->m);
+    p->fused = true;
+    p->net_work.assign((size_t)p->n_nets, 0);
+    std::vector<int32_t> lgn;
+    for (int j = 0; j < p->n_nets; ++j) {
+      const NetCheck &c = chk[(size_t)j];
+      for (size_t k = 0; k < c.sizes.size(); ++k) {
+        const int64_t N = c.sizes[k];
+        int lg = 0;
+        while (lg < 62 && ((int64_t)1 << lg) < N) ++lg;
+        lgn.push_back(std::max(lg, 11));
+        p->net_work[(size_t)j] += N;
+      }
+      p->net_work[(size_t)j] += (int64_t)(c.sizes.size() + 1) / 2 * p->m * p->log2m;  // the pair FFTs
+    }
+    int64_t fc = (int64_t)std::max<size_t>(1, kWorkspaceBudget / std::max<size_t>(1, (size_t)p->W * 4));
+    p->fused_chunk_cap = std::min<int64_t>({fc, p->S, 65535});
+    table_samples = std::max(table_samples, p->fused_chunk_cap);
+    int rc0;
+    if ((rc0 = upload(&p->d_tensor_lgn, lgn)) != TN_OK) return rc0;
+    if ((rc0 = dev_alloc(&p->d_counter, 1)) != TN_OK) return rc0;
+    int fsb = 0;
+    for (int c : {4, 2, 1})
+      if (c <= p->S && m1_fused_lds(c, 1, p->m, (int32_t)worst_cols_rows) + kFusedStatic <= 81920) {
+        fsb = c;
+        break;
+      }
+    if ((rc0 = fused_configure(p, fsb ? fsb : 1, 1)) != TN_OK) return rc0;
+  }
 
   int rc;
   if ((rc = upload(&p->d_streams, p->h_streams)) != TN_OK) return rc;
@@ -145,7 +229,7 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   if ((rc = upload(&p->d_slots, p->h_slots)) != TN_OK) return rc;
   if ((rc = upload(&p->d_tslot, p->h_tslot)) != TN_OK) return rc;
   if ((rc = upload(&p->d_nets, p->h_nets)) != TN_OK) return rc;
-  if ((rc = dev_alloc(&p->d_tables, (size_t)chunk * (size_t)p->W)) != TN_OK) return rc;
+  if ((rc = dev_alloc(&p->d_tables, (size_t)table_samples * (size_t)p->W)) != TN_OK) return rc;
   unsigned char *yb = nullptr;
   if ((rc = dev_alloc(&yb, (size_t)chunk * p->h_slots.size() * (size_t)p->m * as)) != TN_OK) return rc;
   p->d_ybuf = yb;
@@ -174,7 +258,46 @@ int m1_tables(tn_plan *p, int64_t c0, int64_t n, hipStream_t st, const int32_t *
   return rc;
 }
 
+int m1_run_fused(tn_plan *p, hipStream_t st, double *est) {
+  for (int64_t c0 = 0; c0 < p->S; c0 += p->fused_chunk) {
+    const int64_t n = std::min(p->fused_chunk, p->S - c0);
+    const int32_t *tables = nullptr;
+    int rc = m1_tables(p, c0, n, st, &tables);
+    if (rc != TN_OK) return rc;
+    M1FusedLaunch L{};
+    L.items = p->d_items;
+    L.n_items = p->n_items;
+    L.counter = p->d_counter;
+    L.nets = p->d_nets;
+    L.tslot = p->d_tslot;
+    L.slots = p->d_slots;
+    L.tensor_lgn = p->d_tensor_lgn;
+    L.modes = p->d_modes;
+    L.data = p->d_data;
+    L.dtype = p->dtype;
+    L.tables = tables;
+    L.W = p->W;
+    L.chunk = n;
+    L.sample0 = c0;
+    L.S = p->S;
+    L.worst = (int32_t)p->worst_cols_rows;
+    L.sb = p->fused_sb;
+    L.banks = p->fused_banks;
+    L.log2m = p->log2m;
+    L.lds_bytes = p->fused_lds;
+    L.blocks = p->fused_blocks;
+    L.twiddles = p->d_tw;
+    L.est = est;
+    hipEvent_t ev = nullptr;
+    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = launch_m1_fused(L, st)) != TN_OK) return rc;
+    if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
+  }
+  return TN_OK;
+}
+
 int m1_run(tn_plan *p, hipStream_t st, double *est) {
+  if (p->fused) return m1_run_fused(p, st, est);
   for (int64_t c0 = 0; c0 < p->S; c0 += p->chunk) {
     const int64_t n = std::min(p->chunk, p->S - c0);
     const int32_t *tables = nullptr;
@@ -190,6 +313,7 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
     L.W = p->W;
     L.samples = n;
     L.sb = p->sb;
+    L.banks = p->banks;
     L.log2m = p->log2m;
     L.lds_bytes = p->scatter_lds;
     L.ybuf = p->d_ybuf;
@@ -207,70 +331,123 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
   return TN_OK;
 }
 
-// Autotuner of the sketching pass: samples per pass trades one HBM read of the
-// tensors per pass against LDS size (hence blocks per CU).  Each feasible value
-// is timed on the plan's first workspace chunk with the bound data.
+// Autotuner of the sketching pass.  Samples per pass trade one HBM read of the
+// tensors per pass against LDS size (hence blocks per CU); two accumulator
+// banks trade ALU work per term against twice the accumulator LDS.  Each
+// feasible (samples per pass, banks) is timed on the plan's first workspace
+// chunk with the bound data, for the slot kernel or, with TN_FLAG_PERSISTENT,
+// for the persistent kernel.
 struct TuneKey {
   int64_t slots, entries_hint, m, S, W;
   int dtype;
+  bool fused;
   bool operator==(const TuneKey &o) const {
     return slots == o.slots && entries_hint == o.entries_hint && m == o.m && S == o.S && W == o.W &&
-           dtype == o.dtype;
+           dtype == o.dtype && fused == o.fused;
   }
 };
-static std::vector<std::pair<TuneKey, int>> g_tuned;
+static std::vector<std::pair<TuneKey, std::pair<int, int>>> g_tuned;
 
 int m1_autotune(tn_plan *p, hipStream_t st) {
   int64_t entries = 0;
   for (const ScatterSlot &sl : p->h_slots) entries += (int64_t)sl.rows * sl.L;
-  const TuneKey key{(int64_t)p->h_slots.size(), entries, p->m, p->S, p->W, p->dtype};
-  auto apply = [&](int sb) {
+  const TuneKey key{(int64_t)p->h_slots.size(), entries, p->m, p->S, p->W, p->dtype, p->fused};
+  auto apply = [&](int sb, int banks) -> int {
+    if (p->fused) return fused_configure(p, sb, banks);
     p->sb = sb;
-    p->scatter_lds = (size_t)sb * ((size_t)p->m * 8 + 4 * p->worst_cols_rows) + 64;
+    p->banks = banks;
+    p->scatter_lds = scatter_lds_for(p, sb);
+    return TN_OK;
   };
   for (const auto &kv : g_tuned)
-    if (kv.first == key) { apply(kv.second); return TN_OK; }
-  const int64_t n = std::min(p->chunk, p->S);
+    if (kv.first == key) return apply(kv.second.first, kv.second.second);
+  const int64_t n = std::min(p->fused ? p->fused_chunk_cap : p->chunk, p->S);
   const int32_t *tables = nullptr;
   int rc = m1_tables(p, 0, n, st, &tables);
   if (rc != TN_OK) return rc;
   hipEvent_t e0, e1;
   TN_HIP_CHECK(hipEventCreate(&e0));
   TN_HIP_CHECK(hipEventCreate(&e1));
-  int best = p->sb;
+  std::pair<int, int> best{p->fused ? p->fused_sb : p->sb, p->fused ? p->fused_banks : p->banks};
   float best_ms = 1e30f;
-  for (int sb : {1, 2, 4, 8, 16}) {
-    if (sb > 1 && sb > n) break;
-    const size_t lds = (size_t)sb * ((size_t)p->m * 8 + 4 * p->worst_cols_rows) + 64;
-    if (lds > p->max_lds) break;
-    M1Launch L{};
-    L.slots = p->d_slots;
-    L.n_slots = (int64_t)p->h_slots.size();
-    L.modes = p->d_modes;
-    L.data = p->d_data;
-    L.dtype = p->dtype;
-    L.tables = tables;
-    L.W = p->W;
-    L.samples = n;
-    L.sb = sb;
-    L.log2m = p->log2m;
-    L.lds_bytes = lds;
-    L.ybuf = p->d_ybuf;
-    float ms = 0.f;
-    for (int rep = 0; rep < 2 && rc == TN_OK; ++rep) {
-      if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
-      if (rc == TN_OK) rc = launch_m1_scatter(L, st);
-      if (rc == TN_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
-      if (rc == TN_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: sync");
-      if (rc == TN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+  const int sbs_slot[] = {1, 2, 4, 8, 16}, sbs_fused[] = {1, 2, 4};
+  for (int banks : {1, 2}) {
+    for (int sb : p->fused ? std::vector<int>(sbs_fused, sbs_fused + 3) : std::vector<int>(sbs_slot, sbs_slot + 5)) {
+      if (sb > 1 && sb > n) break;
+      float ms = 0.f;
+      if (p->fused) {
+        if (m1_fused_lds(sb, banks, p->m, (int32_t)p->worst_cols_rows) + kFusedStatic > p->max_lds) break;
+        if ((rc = fused_configure(p, sb, banks)) != TN_OK) break;
+      } else {
+        const int save = p->banks;
+        p->banks = banks;
+        const size_t lds = scatter_lds_for(p, sb);
+        p->banks = save;
+        if (lds > p->max_lds) break;
+      }
+      for (int rep = 0; rep < 2 && rc == TN_OK; ++rep) {
+        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
+        if (rc == TN_OK) {
+          if (p->fused) {
+            M1FusedLaunch L{};
+            L.items = p->d_items;
+            L.n_items = p->n_items;
+            L.counter = p->d_counter;
+            L.nets = p->d_nets;
+            L.tslot = p->d_tslot;
+            L.slots = p->d_slots;
+            L.tensor_lgn = p->d_tensor_lgn;
+            L.modes = p->d_modes;
+            L.data = p->d_data;
+            L.dtype = p->dtype;
+            L.tables = tables;
+            L.W = p->W;
+            L.chunk = std::min(n, p->fused_chunk);
+            L.sample0 = 0;
+            L.S = p->S;
+            L.worst = (int32_t)p->worst_cols_rows;
+            L.sb = sb;
+            L.banks = banks;
+            L.log2m = p->log2m;
+            L.lds_bytes = p->fused_lds;
+            L.blocks = p->fused_blocks;
+            L.twiddles = p->d_tw;
+            L.est = p->d_est;  // scratch: overwritten by the estimate that follows
+            rc = launch_m1_fused(L, st);
+          } else {
+            M1Launch L{};
+            L.slots = p->d_slots;
+            L.n_slots = (int64_t)p->h_slots.size();
+            L.modes = p->d_modes;
+            L.data = p->d_data;
+            L.dtype = p->dtype;
+            L.tables = tables;
+            L.W = p->W;
+            L.samples = n;
+            L.sb = sb;
+            L.banks = banks;
+            L.log2m = p->log2m;
+            p->banks = banks;
+            L.lds_bytes = scatter_lds_for(p, sb);
+            L.ybuf = p->d_ybuf;
+            rc = launch_m1_scatter(L, st);
+          }
+        }
+        if (rc == TN_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
+        if (rc == TN_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: sync");
+        if (rc == TN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (rc != TN_OK) break;
+      // per sample of the chunk, so that candidates with different chunks compare
+      const float per = ms / (float)(p->fused ? std::min(n, p->fused_chunk) : n);
+      if (per < best_ms) { best_ms = per; best = {sb, banks}; }
     }
     if (rc != TN_OK) break;
-    if (ms < best_ms) { best_ms = ms; best = sb; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc != TN_OK) return rc;
-  apply(best);
+  if ((rc = apply(best.first, best.second)) != TN_OK) return rc;
   g_tuned.push_back({key, best});
   return TN_OK;
 }
@@ -473,8 +650,9 @@ void plan_release(tn_plan *p) {
   p->graph_exec = nullptr;
   p->graph = nullptr;
   if (p->m2) m2_release(p);
-  void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data, p->d_modes, p->d_slots,
-                  p->d_tslot,   p->d_nets,   p->d_tw,       p->d_ybuf, p->d_est};
+  void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data,    p->d_modes,
+                  p->d_slots,   p->d_tslot,  p->d_nets,     p->d_tw,      p->d_ybuf,
+                  p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p->d_streams = nullptr;
@@ -486,6 +664,8 @@ void plan_release(tn_plan *p) {
   p->d_nets = nullptr;
   p->d_tw = p->d_ybuf = nullptr;
   p->d_est = nullptr;
+  p->d_items = nullptr;
+  p->d_counter = p->d_tensor_lgn = nullptr;
 }
 
 int64_t plan_query(const tn_plan *p, int key) {
@@ -498,8 +678,10 @@ int64_t plan_query(const tn_plan *p, int key) {
     case 5: return p->n_tensors;
     case 6: return p->n_tensors;
     case 7: return p->method;
-    case 8: return p->sb;
-    case 9: return p->chunk;
+    case 8: return p->fused ? p->fused_sb : p->sb;
+    case 9: return p->fused ? p->fused_chunk : p->chunk;
+    case 10: return p->method == TN_CYCLIC ? (p->fused ? p->fused_banks : p->banks) : 0;
+    case 11: return p->fused ? 1 : 0;
     default: return set_error(TN_ERR_ARG, "unknown query key %d", key);
   }
 }
@@ -567,6 +749,7 @@ int plan_get_sketches(tn_plan *p, const tn_network *nets, int64_t first, int64_t
     L.W = p->W;
     L.samples = n;
     L.sb = p->sb;
+    L.banks = p->banks;
     L.log2m = p->log2m;
     L.lds_bytes = p->scatter_lds;
     L.ybuf = p->d_ybuf;

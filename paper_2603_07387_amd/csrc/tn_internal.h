@@ -86,10 +86,47 @@ struct M1Launch {
   int64_t W;
   int64_t samples;           // samples in this chunk
   int sb;                    // samples per scatter block
+  int banks;                 // accumulator banks per sketch (1: signed adds, 2: sign in the address)
   int log2m;
   size_t lds_bytes;
   void *ybuf;                // [samples][n_slots][m] (double for F64, float otherwise)
 };
+
+// Persistent fused kernel: one work item = (network, first sample of a batch
+// of up to `sb` samples within the launch's chunk), sorted by decreasing work.
+struct FusedItem {
+  int32_t net;
+  int32_t s0;
+};
+
+struct M1FusedLaunch {
+  const FusedItem *items;
+  int32_t n_items;
+  int32_t *counter;           // one int of device memory (reset by the launch)
+  const NetDesc *nets;
+  const int32_t *tslot;       // per tensor: first slot; [n_tensors + 1]
+  const ScatterSlot *slots;
+  const int32_t *tensor_lgn;  // per tensor: max(ceil(log2(entries)), 11)
+  const ModeDesc *modes;
+  const void *const *data;
+  int dtype;
+  const int32_t *tables;      // [chunk][W]
+  int64_t W;
+  int64_t chunk;              // samples in this launch
+  int64_t sample0;
+  int64_t S;
+  int32_t worst;              // max over slots of rows + L
+  int sb;                     // samples per item (1, 2, 4)
+  int banks;                  // accumulator banks per sketch (1 or 2, see the slot scatter)
+  int log2m;
+  size_t lds_bytes;
+  int64_t blocks;             // persistent grid
+  const void *twiddles;
+  double *est;
+};
+
+size_t m1_fused_lds(int sb, int banks, int64_t m, int32_t worst);
+int launch_m1_fused(const M1FusedLaunch &L, hipStream_t st);
 
 int launch_hashgen(const StreamDesc *streams, int64_t n_streams, int64_t W, int64_t sample0,
                    int64_t samples, int64_t m, int32_t *out, hipStream_t st);
