@@ -30,8 +30,10 @@ using namespace m1dev;
 
 // One block streams one slot and accumulates the sketches of SB samples (see
 // scatter_slot), then writes them out as floating point.
+// Blocks of 256 threads with one bank, 512 with two (twice the accumulator LDS
+// per block, the same waves per CU).
 template <typename T, typename A, int SB, int BANKS>
-__global__ __launch_bounds__(256) void m1_scatter_kernel(
+__global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
     int64_t samples, int log2m, int64_t n_slots, A *__restrict__ ybuf) {
@@ -48,15 +50,16 @@ __global__ __launch_bounds__(256) void m1_scatter_kernel(
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
   uint32_t *colt = reinterpret_cast<uint32_t *>(smem + ((acc_bytes + 15) & ~(size_t)15));  // [SB][L]
   uint32_t *rowt = colt + SB * sl.L;                                                     // [SB][rows]
-  for (int i = tid; i < (int)(acc_bytes / 8); i += 256) acc[i] = 0ull;
+  constexpr int NT = 256 * BANKS;
+  for (int i = tid; i < (int)(acc_bytes / 8); i += NT) acc[i] = 0ull;
   if (tid < 2) s_max[tid] = 0ull;
   const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
   FixedScale fs;
   fs.lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
-  scatter_slot<T, SB, BANKS>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * m, signbit, colt,
+  scatter_slot<T, SB, BANKS, NT>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * m, signbit, colt,
                              rowt, s_max, fs);
   const unsigned long long *neg = acc + signbit / 8;
-  for (int i = tid; i < nsb * (int)m; i += 256) {
+  for (int i = tid; i < nsb * (int)m; i += NT) {
     const int s = i >> log2m;
     const int b = i & mask;
     // positive bank minus negative bank
@@ -187,7 +190,7 @@ int scatter_sb(const M1Launch &L, hipStream_t st) {
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)L.lds_bytes));
   dim3 grid((unsigned)L.n_slots, (unsigned)((L.samples + SB - 1) / SB));
-  hipLaunchKernelGGL(kern, grid, dim3(256), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
+  hipLaunchKernelGGL(kern, grid, dim3(256 * L.banks), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
                      L.W, L.samples, L.log2m, L.n_slots, reinterpret_cast<A *>(L.ybuf));
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;

@@ -120,9 +120,9 @@ __host__ __device__ constexpr size_t sign_bank_bytes(int sb, uint32_t m) {
 // Builds the slot's packed row and column tables in rowt / colt (LDS, SB x
 // rows and SB x L words), then streams the slot once from HBM with 16-byte
 // loads.  s_max (2 words of LDS) holds the running maximum; both it and fs
-// carry over between calls that feed the same sketches.  Every thread of the
-// block calls it; it starts and ends with a barrier.
-template <typename T, int SB, int BANKS>
+// carry over between calls that feed the same sketches.  All NT threads of
+// the block call it; it starts and ends with a barrier.
+template <typename T, int SB, int BANKS, int NT>
 __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDesc *__restrict__ modes,
                                              const void *const *__restrict__ data,
                                              const int32_t *__restrict__ tables, int64_t W, int nsb,
@@ -133,16 +133,17 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
   const uint32_t m = 1u << log2m, mask = m - 1;
   const int L = sl.L, rows = sl.rows;
   auto to_offset = [signbit](uint32_t v) {
+    (void)signbit;  // unused with one bank
     if constexpr (BANKS == 2) return ((v & ~kSignBit) << 3) + ((v & kSignBit) ? signbit : 0u);
     else return ((v & ~kSignBit) << 3) | (v & kSignBit);  // sign stays in bit 31
   };
   __syncthreads();  // earlier readers of the tables are done
-  for (int i = tid; i < nsb * L; i += 256) {
+  for (int i = tid; i < nsb * L; i += NT) {
     const int s = i / L, c = i - s * L;
     colt[s * L + c] = to_offset(combine_modes(tables + s * W, modes, sl.mode0 + sl.split,
                                               sl.mode0 + sl.q - 1, c, m, mask));
   }
-  for (int i = tid; i < nsb * rows; i += 256) {
+  for (int i = tid; i < nsb * rows; i += NT) {
     const int s = i / rows, r = i - s * rows;
     rowt[s * rows + r] = to_offset(combine_modes(tables + s * W, modes, sl.mode0,
                                                  sl.mode0 + sl.split - 1,
@@ -170,7 +171,7 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       const int ns = 62 - fs.lgN - e;
       if (fs.bound > 0.0 && fs.scale > ns) {
         const int d = fs.scale - ns;
-        for (int i = tid; i < BANKS * nsb * (int)m; i += 256) {
+        for (int i = tid; i < BANKS * nsb * (int)m; i += NT) {
           const int si = BANKS == 2 ? i >> (log2m + 1) : i >> log2m;
           const int bank = BANKS == 2 ? (i >> log2m) & 1 : 0, b = i & (int)mask;
           unsigned long long *w = reinterpret_cast<unsigned long long *>(
@@ -228,12 +229,12 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
     const V __attribute__((address_space(1))) *Xv =
         (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X);
     const uint32_t NV = N / VEC;
-    for (uint32_t v0 = 0; v0 < NV; v0 += 256 * UNROLL) {
+    for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
       // Unconditional loads (index clamped into the slot) keep all UNROLL loads
       // in flight; out-of-range lanes are masked when the values are used.
       V buf[UNROLL];
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) buf[u] = Xv[min(v0 + u * 256 + tid, NV - 1)];
+      for (int u = 0; u < UNROLL; ++u) buf[u] = Xv[min(v0 + u * NT + tid, NV - 1)];
       double lmax = 0.0;
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
@@ -245,7 +246,7 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       uint32_t rr[UNROLL], cc[UNROLL];
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
-        const uint32_t e = min(v0 + u * 256 + tid, NV - 1) * VEC;  // clamped: valid table reads
+        const uint32_t e = min(v0 + u * NT + tid, NV - 1) * VEC;  // clamped: valid table reads
         rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
         cc[u] = e - rr[u] * (uint32_t)L;
       }
@@ -256,7 +257,7 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
-        if (v0 + u * 256 + tid < NV) {
+        if (v0 + u * NT + tid < NV) {
           const T *xs = reinterpret_cast<const T *>(&buf[u]);
           long long q[VEC];
 #pragma unroll
@@ -273,17 +274,17 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
   } else {
     const T __attribute__((address_space(1))) *Xg =
         (const T __attribute__((address_space(1))) *)X;
-    for (uint32_t e0 = 0; e0 < N; e0 += 256 * UNROLL) {
+    for (uint32_t e0 = 0; e0 < N; e0 += NT * UNROLL) {
       T buf[UNROLL];
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) buf[u] = Xg[min(e0 + u * 256 + tid, N - 1)];
+      for (int u = 0; u < UNROLL; ++u) buf[u] = Xg[min(e0 + u * NT + tid, N - 1)];
       double lmax = 0.0;
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) lmax = fmax(lmax, fabs((double)to_acc_any(buf[u])));
       update_scale(lmax);
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
-        const uint32_t e = e0 + u * 256 + tid;
+        const uint32_t e = e0 + u * NT + tid;
         if (e < N) {
           const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
           scatter_one((double)to_acc_any(buf[u]), r, e - r * (uint32_t)L);
