@@ -308,24 +308,48 @@ struct Cplx<double> {
 
 // In-place radix-2 decimation-in-time FFT of M points held in LDS in
 // bit-reversed order; natural-order output.  F[j][b] = exp(-2 pi i j b / M).
+// Stages are taken two at a time: a thread carries the four points of a
+// radix-2^2 group through both stages in registers (the same butterflies and
+// twiddles as two radix-2 passes), which halves the barriers and LDS passes; an
+// odd stage count starts with one single stage.
 template <typename A, int LOG2M>
 __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
                                         const typename Cplx<A>::type *__restrict__ tw) {
   constexpr int M = 1 << LOG2M;
   using A2 = typename Cplx<A>::type;
-#pragma unroll 1
-  for (int lg = 1; lg <= LOG2M; ++lg) {
-    const int half = 1 << (lg - 1);
+  auto bfly = [](A2 &za, A2 &zb, const A2 w) {
+    const A tr = w.x * zb.x - w.y * zb.y;
+    const A ti = w.x * zb.y + w.y * zb.x;
+    zb = A2{za.x - tr, za.y - ti};
+    za = A2{za.x + tr, za.y + ti};
+  };
+  int lg = 1;
+  if constexpr ((LOG2M & 1) != 0) {
     for (int q = threadIdx.x; q < M / 2; q += 256) {
-      const int k = q & (half - 1);
-      const int a = ((q >> (lg - 1)) << lg) + k;
-      const int b = a + half;
-      const A2 w = tw[k << (LOG2M - lg)];
-      const A2 za = z[a], zb = z[b];
-      const A tr = w.x * zb.x - w.y * zb.y;
-      const A ti = w.x * zb.y + w.y * zb.x;
-      z[a] = A2{za.x + tr, za.y + ti};
-      z[b] = A2{za.x - tr, za.y - ti};
+      A2 za = z[2 * q], zb = z[2 * q + 1];
+      bfly(za, zb, tw[0]);
+      z[2 * q] = za;
+      z[2 * q + 1] = zb;
+    }
+    __syncthreads();
+    lg = 2;
+  }
+#pragma unroll 1
+  for (; lg < LOG2M; lg += 2) {
+    const int h = 1 << (lg - 1);
+    for (int q = threadIdx.x; q < M / 4; q += 256) {
+      const int k = q & (h - 1);
+      const int base = ((q >> (lg - 1)) << (lg + 1)) + k;
+      A2 z0 = z[base], z1 = z[base + h], z2 = z[base + 2 * h], z3 = z[base + 3 * h];
+      const A2 w1 = tw[k << (LOG2M - lg)];
+      bfly(z0, z1, w1);  // stage lg: (base, base + h), (base + 2h, base + 3h)
+      bfly(z2, z3, w1);
+      bfly(z0, z2, tw[k << (LOG2M - lg - 1)]);  // stage lg + 1: (base, base + 2h), (base + h, base + 3h)
+      bfly(z1, z3, tw[(k + h) << (LOG2M - lg - 1)]);
+      z[base] = z0;
+      z[base + h] = z1;
+      z[base + 2 * h] = z2;
+      z[base + 3 * h] = z3;
     }
     __syncthreads();
   }
