@@ -37,8 +37,9 @@ __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
     int64_t samples, int log2m, int64_t n_slots, A *__restrict__ ybuf) {
+  // No static LDS: the accumulators start at LDS address 0, so their offsets
+  // need no base add per term.
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ unsigned long long s_max[2];
   const ScatterSlot sl = slots[blockIdx.x];
   const int tid = threadIdx.x;
   const int64_t s0 = (int64_t)blockIdx.y * SB;
@@ -47,9 +48,11 @@ __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
   // BANKS banks of m words per sample (see scatter_slot), then the tables
   const uint32_t signbit = BANKS == 2 ? sign_bank_offset(SB, m) : 0u;
   const size_t acc_bytes = BANKS == 2 ? sign_bank_bytes(SB, m) : (size_t)SB * 8 * m;
+  const size_t acc_end = (acc_bytes + 15) & ~(size_t)15;
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
-  uint32_t *colt = reinterpret_cast<uint32_t *>(smem + ((acc_bytes + 15) & ~(size_t)15));  // [SB][L]
-  uint32_t *rowt = colt + SB * sl.L;                                                     // [SB][rows]
+  unsigned long long *s_max = reinterpret_cast<unsigned long long *>(smem + acc_end);  // [2]
+  uint32_t *colt = reinterpret_cast<uint32_t *>(smem + acc_end + 16);                  // [SB][L]
+  uint32_t *rowt = colt + SB * sl.L;                                                   // [SB][rows]
   constexpr int NT = 256 * BANKS;
   for (int i = tid; i < (int)(acc_bytes / 8); i += NT) acc[i] = 0ull;
   if (tid < 2) s_max[tid] = 0ull;

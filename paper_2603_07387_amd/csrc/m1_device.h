@@ -192,23 +192,24 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
     return __double_as_longlong(fma(x, fs.sc, kMagic)) - __double_as_longlong(kMagic);
   };
   // One fixed-point add into sample s's sketch (its sign selects the bank).
-  auto add_fixed = [&](int s, uint32_t hv, uint32_t lv, long long v) {
+  // (nv = -v, formed once per entry for all samples of the batch.)
+  auto add_fixed = [&](int s, uint32_t hv, uint32_t lv, long long v, long long nv) {
     const uint32_t a = ((hv + lv) & amask) + (uint32_t)s * sbytes;
     if constexpr (BANKS == 2)
       atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + a), (unsigned long long)v);
     else
       atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + a),
-                (unsigned long long)(((hv ^ lv) & kSignBit) ? -v : v));
+                (unsigned long long)(((hv ^ lv) & kSignBit) ? nv : v));
   };
   // Add entry x (row r, column c) to the sketch of every sample of the batch.
   auto scatter_one = [&](double x, uint32_t r, uint32_t c) {
-    const long long v = to_fixed(x);
+    const long long v = to_fixed(x), nv = -v;
     uint32_t hv[SB], lv[SB];
 #pragma unroll
     for (int s = 0; s < SB; ++s) { hv[s] = rowt[s * rows + r]; lv[s] = colt[s * L + c]; }
 #pragma unroll
     for (int s = 0; s < SB; ++s)
-      if (s < nsb) add_fixed(s, hv[s], lv[s], v);
+      if (s < nsb) add_fixed(s, hv[s], lv[s], v, nv);
   };
   constexpr int VEC = 16 / (int)sizeof(T);   // entries per 16-byte load
   // Row and column entries of every sample for VEC consecutive entries of one
@@ -259,14 +260,17 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
         if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
         if (v0 + u * NT + tid < NV) {
           const T *xs = reinterpret_cast<const T *>(&buf[u]);
-          long long q[VEC];
+          long long q[VEC], nq[VEC];
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) q[i] = to_fixed((double)to_acc_any(xs[i]));
+          for (int i = 0; i < VEC; ++i) {
+            q[i] = to_fixed((double)to_acc_any(xs[i]));
+            nq[i] = BANKS == 2 ? 0 : -q[i];
+          }
 #pragma unroll
           for (int s = 0; s < SB; ++s)
             if (s < nsb) {
 #pragma unroll
-              for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i]);
+              for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i], nq[i]);
             }
         }
       }

@@ -170,6 +170,17 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   for (int sb : {8, 4, 2}) {
     if (sb <= p->S && lds_for(sb) <= 81920) { p->sb = sb; break; }
   }
+  // Overrides of the untuned schedule (tests and tuning experiments; the
+  // autotuner, when requested, still decides).
+  if (const char *env = getenv("TN_SCATTER_BANKS")) {
+    const int banks = atoi(env);
+    if (banks == 1 || banks == 2) {
+      const int save = p->banks;
+      p->banks = banks;
+      if (lds_for(1) > p->max_lds) p->banks = save;
+      else if (lds_for(p->sb) > 81920) p->sb = 1;
+    }
+  }
   if (const char *env = getenv("TN_SCATTER_SB")) {
     const int sb = atoi(env);
     if ((sb == 1 || sb == 2 || sb == 4 || sb == 8 || sb == 16) && lds_for(sb) <= p->max_lds) p->sb = sb;

@@ -212,21 +212,55 @@ def test_graph_replay(T, orc):
         del junk
 
 
-def test_bitwise_deterministic_across_schedules(T, orc):
+def test_bitwise_deterministic_across_schedules(T, orc, monkeypatch):
     """Fixed-point sketch accumulation: estimates are bit-identical run to run and
-    for every samples-per-pass choice of the autotuner."""
+    for every samples-per-pass choice with one accumulator bank.  The two-bank
+    layout (512-thread blocks) may rescale its accumulators at other points and
+    shifts the two banks separately, so it agrees to the fixed-point resolution
+    (2^-46 of the slot's max |x| per term), far inside the oracle bar."""
     nets = [W.torus(L=2, D=16, seed=9), W.random_network(4, 3)]
-    a, views = make_plan(T, nets, "float32", 1024, 24, 8)
-    b, _ = make_plan(T, nets, "float32", 1024, 24, 8, flags=T.TN_FLAG_AUTOTUNE)
-    _, ga = run(a)
-    _, ga2 = run(a)
-    _, gb = run(b)
-    assert np.array_equal(ga, ga2)
-    assert np.array_equal(ga, gb)
-    assert b.query(8) in (1, 2, 4, 8, 16)
+    monkeypatch.setenv("TN_SCATTER_BANKS", "1")
+    runs = []
+    for sb in ("1", "2", "4", "8"):
+        monkeypatch.setenv("TN_SCATTER_SB", sb)
+        p, views = make_plan(T, nets, "float32", 1024, 24, 8)
+        assert p.query(8) == int(sb) and p.query(10) == 1
+        _, g = run(p)
+        _, g2 = run(p)
+        assert np.array_equal(g, g2)
+        runs.append(g)
+    for g in runs[1:]:
+        assert np.array_equal(runs[0], g)
+    monkeypatch.delenv("TN_SCATTER_SB")
+    monkeypatch.setenv("TN_SCATTER_BANKS", "2")
+    p2, _ = make_plan(T, nets, "float32", 1024, 24, 8)
+    assert p2.query(10) == 2
+    _, g2b = run(p2)
     for j, net in enumerate(views):
         ref, scale = oracle_samples(orc, net, 1024, 8 + j, range(3))
-        assert np.all(np.abs(ga[j, :3] - ref) <= 1e-5 * scale)
+        assert np.all(np.abs(runs[0][j, :3] - ref) <= 1e-5 * scale)
+        assert np.all(np.abs(g2b[j, :3] - ref) <= 1e-5 * scale)
+        assert np.all(np.abs(g2b[j] - runs[0][j]) <= 1e-9 * np.abs(runs[0][j]).max())
+    monkeypatch.delenv("TN_SCATTER_BANKS")
+    b, _ = make_plan(T, nets, "float32", 1024, 24, 8, flags=T.TN_FLAG_AUTOTUNE)
+    _, gb = run(b)
+    assert b.query(8) in (1, 2, 4, 8, 16) and b.query(10) in (1, 2)
+    assert np.all(np.abs(gb - runs[0]) <= 1e-9 * np.abs(runs[0]).max())
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32", "bfloat16"])
+def test_two_bank_scatter_parity(T, orc, dtype, monkeypatch):
+    """The two-bank accumulators (sign in the address) against the oracle: sketches
+    within tau * A_b and estimates within tau * A_hat, on multi-slot tensors, a
+    ragged sample batch and m = 64 / 4096."""
+    monkeypatch.setenv("TN_SCATTER_BANKS", "2")
+    big = W.Network([3, 3], [50, 40, 60, 60, 40, 50], [(0, 5), (1, 4), (2, 3)],
+                    [np.random.default_rng(5).standard_normal((50, 40, 60)),
+                     np.random.default_rng(6).standard_normal((60, 40, 50))])
+    for m, S in ((64, 5), (4096, 3)):
+        plan, views = make_plan(T, [W.triangle(16, seed=3), big, W.random_network(4, 11)], dtype, m, S, 21)
+        assert plan.query(10) == 2
+        check_estimates(orc, plan, views, 21, dtype)
 
 
 def _brute_force_sized(count, limit=5e7):
