@@ -231,7 +231,8 @@ def main():
         achieved = flops_step / (sk_ms / a.steps * 1e-3) / 1e12
         peak = BF16_MFMA_PEAK_TFLOPS if bf16_products else FP64_MFMA_PEAK_TFLOPS
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "kernel": "m2_gemm_kernel",
+                "frac": achieved / peak, "traffic": None,
+                "kernel": "m2_gemm_bf16_kernel" if bf16_products else "m2_gemm16_kernel",
                 "avg_launch_ms": avg_ms, "launches": sk_n, "flops_per_step": flops_step}
     st = stats.cpu().numpy().reshape(-1, 2)
     norms = np.array([n.input_norm() for n in nets])

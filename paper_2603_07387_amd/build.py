@@ -28,9 +28,16 @@ CFLAGS = [
 ]
 
 
+# Per-source extras.  m2.hip: matrix-instruction accumulators in ordinary VGPRs;
+# otherwise the compiler keeps the loop-carried accumulators of the FP64
+# products in VGPRs and copies them to and from AGPRs around every chunk, which
+# drains the matrix pipeline once per chunk.
+EXTRA = {"m2.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -26,10 +26,11 @@
 //               scatter of the children's Kronecker products into an LDS
 //               fixed-point sketch r_k, then the gather g over the child index
 //               space, written to HBM.
-//   m2_gemm   : w_k = mat(X_k) G over all samples of the chunk on the FP64
+//   m2_gemm16 : w_k = mat(X_k) G over all samples of the chunk on the FP64
 //               matrix cores (operands widened exactly, FP64 accumulation),
-//               blocks of 64 rows x 16 samples, columns optionally split over
-//               wave groups and summed in a fixed order.
+//               blocks of 64 rows x 64 samples staged through LDS; on levels
+//               with few tiles the columns are split over blocks and the FP64
+//               partials summed in a fixed order by m2_reduce.
 #include <algorithm>
 #include <new>
 #include <queue>
@@ -80,6 +81,9 @@ struct M2Plan {
   std::vector<std::vector<int32_t>> level_nodes;  // per depth: nodes with children
   std::vector<std::vector<M2Tile>> level_tiles;
   std::vector<int64_t> level_maxcols;             // per depth: widest node
+  std::vector<int32_t> level_splits;              // per depth: column ranges of the FP64 product
+  std::vector<int32_t> level_kcols;               // per depth: columns per range
+  double *d_part = nullptr;                       // column-split partials (largest level)
   std::vector<int32_t *> d_level_nodes;
   std::vector<M2Tile *> d_level_tiles;
   int64_t g_row = 0;    // entries of g per sample (max over depths)
@@ -341,20 +345,7 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// w_k = mat(X_k) G on the FP64 matrix cores with v_mfma_f64_4x4x4f64: four
-// independent 4x4x4 blocks per instruction, lane layout (measured)
-//   A[b][i][k] in lane 16k + 4b + i,  B[b][k][j] in lane 16k + 4b + j,
-//   D[b][i][j] in lane 16i + 4b + j.
-// The block index b carries four disjoint column sets, summed across lanes at
-// the end, so no operand is replicated.  A wave owns 16 rows (four groups rho
-// of 4) x 16 samples (four groups gamma of 4); lane (i, b, k) takes row
-// 4 rho + i of X and sample 4 gamma + i of G in column slot sigma = 4b + k, i.e.
-// the W consecutive columns c0 + W sigma .. + W - 1 of each chunk of 16 W
-// columns; step t contracts column c0 + W sigma + t.  One step is 16 matrix
-// instructions (rho x gamma) on 4 + 4 operand registers.  Operands are widened
-// to FP64 (exact) and accumulated in FP64.  Block: four waves (64 rows) x 16
-// samples; KSPLIT groups of four waves take interleaved chunks and are summed
-// in a fixed order in LDS (deterministic).
+// w_k = mat(X_k) G: operand loads shared by the matrix-core products below.
 typedef float gf32x4 __attribute__((ext_vector_type(4)));
 typedef double gf64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short gu16x4 __attribute__((ext_vector_type(4)));
@@ -404,151 +395,239 @@ struct RawW<uint16_t> {
 constexpr int kGemmRows = 64;     // rows per block (four waves of 16)
 constexpr int kGemmSamples = 16;  // samples per block
 
-template <typename T, typename A, int KSPLIT>
-__global__ __launch_bounds__(256 * KSPLIT) void m2_gemm_kernel(
-    const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, const void *const *data,
-    const A *__restrict__ gbuf, int64_t g_row, int64_t samples, A *__restrict__ wbuf,
-    int64_t w_row, double *__restrict__ est, int64_t S, int64_t sample0) {
+// ---------------------------------------------------------------------------
+// The FP64 product on v_mfma_f64_16x16x4f64 (A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, D[i][j] as element i / 4 of lane j + 16 (i % 4)).  A block of four
+// waves owns 64 rows x 64 samples and a column range; each wave a 32 x 32 corner
+// (2 x 2 accumulators of 16 x 16).  Per chunk of 16 W columns the block stages the
+// X rows and the G rows in double-buffered LDS, one 16-byte vector (W columns) per
+// (row, slot), with the next chunk's global loads in flight during the matrix
+// instructions.  Lane (i, kk) takes slots kk + 4q: column W (kk + 4q) + e of the
+// chunk enters instruction (q, e) at contraction index kk, so every column of
+// the chunk is summed once.  The 64 x 64 result goes through LDS to coalesced
+// stores: FP64 partials [split][tile][sample][64] when the columns are split,
+// else w or the estimates.
+constexpr int kG16Rows = 64, kG16Samples = 64, kG16Threads = 256, kG16Pad = 17;
+
+template <typename T, typename A>
+constexpr size_t g16_lds_bytes() {
+  constexpr size_t tiles = (size_t)2 * kG16Pad * (kG16Rows * sizeof(RawW<T>) + kG16Samples * sizeof(RawW<A>));
+  constexpr size_t outb = (size_t)kG16Samples * (kG16Rows + 1) * sizeof(double);
+  return tiles > outb ? tiles : outb;
+}
+
+template <typename T, typename A>
+__global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
+    const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, int32_t n_tiles,
+    const void *const *data, const A *__restrict__ gbuf, int64_t g_row, int64_t samples,
+    A *__restrict__ wbuf, int64_t w_row, double *__restrict__ est, int64_t S, int64_t sample0,
+    int32_t kcols, double *__restrict__ part) {
   constexpr int W = RawW<T>::W;
   static_assert(RawW<A>::W == W, "operand widths differ");
-  constexpr int32_t kChunk = 16 * W;
-  constexpr int32_t kStep = kChunk * KSPLIT;
-  __shared__ double red[KSPLIT > 1 ? (KSPLIT - 1) * 256 * 4 : 1];
+  constexpr int32_t CC = 16 * W;  // columns per chunk
+  constexpr int ROWV = kG16Pad;   // vectors per LDS row (16 + 1 pad)
+  using V = RawW<T>;
+  using VA = RawW<A>;
+  extern __shared__ __align__(16) unsigned char g16_smem[];
+  V *Xs = reinterpret_cast<V *>(g16_smem);                                     // [2][64][ROWV]
+  VA *Gs = reinterpret_cast<VA *>(g16_smem + (size_t)2 * kG16Rows * ROWV * sizeof(V));  // [2][64][ROWV]
   const M2Tile tl = tiles[blockIdx.x];
   const M2Node &nd = nodes[tl.node];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rt = wave & 3, kg = wave >> 2;
-  const int lo = lane & 3, bq = (lane >> 2) & 3, kq = lane >> 4;
-  const int sigma = 4 * bq + kq;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave & 1, ws = wave >> 1;
+  const int li = lane & 15, kk = lane >> 4;
   const int64_t rows = nd.rows, after = nd.after;
-  const int32_t ncols = (int32_t)nd.ncols;  // below 2^31 (planner)
-  const int64_t row0 = (int64_t)tl.row0 + rt * 16 + lo;              // + 4 rho
-  const int64_t smp0 = (int64_t)blockIdx.y * kGemmSamples + lo;      // + 4 gamma
+  const int32_t ncols = (int32_t)nd.ncols;
+  const int64_t s_base = (int64_t)blockIdx.y * kG16Samples;
   const void *X = data[nd.tensor];
-  bool row_ok[4], smp_ok[4];
+  const int32_t c_begin = (int32_t)blockIdx.z * kcols;
+  const int32_t c_end = min(ncols, c_begin + kcols);
+  // loads: slot lv of rows / samples lr + 16 p, p = 0..3
+  const int lv = tid & 15, lr = tid >> 4;
+  bool xok[4], gok[4];
+  const A *grow[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    row_ok[r] = row0 + 4 * r < rows;
-    smp_ok[r] = smp0 + 4 * r < samples;
+  for (int p = 0; p < 4; ++p) {
+    xok[p] = (int64_t)tl.row0 + lr + 16 * p < rows;
+    gok[p] = s_base + lr + 16 * p < samples;
+    grow[p] = gbuf + (gok[p] ? s_base + lr + 16 * p : 0) * g_row + nd.g_off;
   }
-  const A *g0 = gbuf + (smp_ok[0] ? smp0 : 0) * g_row + nd.g_off;
-  const int64_t g4 = 4 * g_row;        // next sample group
-  const int64_t x4 = 4 * after;        // next row group
-  // W consecutive columns in one contiguous run of X, and alignment of X.
   const bool vec = (after % W) == 0 &&
                    (reinterpret_cast<uintptr_t>(X) & (uintptr_t)(W * sizeof(T) - 1)) == 0;
-  // Column c = c0 + W sigma of this lane; its X offset for row r is
-  // ((c / after) rows + r) after + c % after, tracked incrementally.
-  int32_t c = kg * kChunk + W * sigma;
   const int32_t after32 = (int32_t)after;
+  int32_t c = c_begin + W * lv;
   int32_t qd = c / after32, rm = c - qd * after32;
-  const int32_t stepq = kStep / after32, stepr = kStep - stepq * after32;
-  auto load_chunk = [&](RawW<T> *xa, RawW<A> *gb) {
-    const int64_t xo = ((int64_t)qd * rows + row0) * after + rm;
-    if (vec && c + W - 1 < ncols) {
+  const int32_t stepq = CC / after32, stepr = CC - stepq * after32;
+  V xreg[4];
+  VA greg[4];
+  auto load_chunk = [&]() {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (row_ok[r]) xa[r].load(X, xo + r * x4);
-        else xa[r] = RawW<T>{};
-        if (smp_ok[r]) gb[r].load(g0 + r * g4, c);
-        else gb[r] = RawW<A>{};
+    for (int p = 0; p < 4; ++p) {
+      xreg[p] = V{};
+      greg[p] = VA{};
+    }
+    const int64_t x0 = ((int64_t)qd * rows + tl.row0 + lr) * after + rm;
+    if (vec && c + W - 1 < c_end) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        if (xok[p]) xreg[p].load(X, x0 + 16 * p * after);
+        if (gok[p]) greg[p].load(grow[p], c);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        xa[r] = RawW<T>{};
-        gb[r] = RawW<A>{};
-      }
-#pragma unroll
       for (int e = 0; e < W; ++e) {
         const int32_t ce = c + e;
-        if (ce < ncols) {
+        if (ce < c_end) {
           const int32_t qe = ce / after32;
-          const int64_t xe = ((int64_t)qe * rows + row0) * after + (ce - qe * after32);
+          const int64_t xe = ((int64_t)qe * rows + tl.row0 + lr) * after + (ce - qe * after32);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (row_ok[r]) xa[r].set(e, X, xe + r * x4);
-            if (smp_ok[r]) gb[r].set(e, g0 + r * g4, ce);
+          for (int p = 0; p < 4; ++p) {
+            if (xok[p]) xreg[p].set(e, X, xe + 16 * p * after);
+            if (gok[p]) greg[p].set(e, grow[p], ce);
           }
         }
       }
     }
   };
   auto next_chunk = [&]() {
-    c += kStep;
+    c += CC;
     qd += stepq;
     rm += stepr;
     if (rm >= after32) { rm -= after32; ++qd; }
   };
-  double acc[4][4];
+  auto store_chunk = [&](int buf) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+    for (int p = 0; p < 4; ++p) {
+      Xs[((size_t)buf * kG16Rows + lr + 16 * p) * ROWV + lv] = xreg[p];
+      Gs[((size_t)buf * kG16Samples + lr + 16 * p) * ROWV + lv] = greg[p];
+    }
+  };
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc[2][2];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) acc[r][g] = 0.0;
-  // The trip count must be the same for all lanes of the wave (the matrix
-  // instruction works on the whole wave): loop over the chunk base, predicate
-  // the loads per lane.  Four or more waves per SIMD hide the load latency
-  // (holding the next chunk in registers as well costs occupancy and measured
-  // no faster).
-  RawW<T> xa[4];
-  RawW<A> gb[4];
-  for (int32_t cb = kg * kChunk; cb < ncols; cb += kStep) {
-    load_chunk(xa, gb);
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-      double av[4], bv[4];
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  int buf = 0;
+  if (c_begin < c_end) {
+    load_chunk();
+    store_chunk(0);
+  }
+  __syncthreads();
+  for (int32_t cb = c_begin; cb < c_end; cb += CC) {
+    const bool more = cb + CC < c_end;  // the same in every thread
+    if (more) {
+      next_chunk();
+      load_chunk();
+    }
+    const V *xb = Xs + ((size_t)buf * kG16Rows + wr * 32 + li) * ROWV + kk;
+    const VA *gbp = Gs + ((size_t)buf * kG16Samples + ws * 32 + li) * ROWV + kk;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        av[r] = xa[r].get(t);
-        bv[r] = gb[r].get(t);
+    for (int q = 0; q < 4; ++q) {
+      const V a0 = xb[4 * q], a1 = xb[16 * ROWV + 4 * q];
+      const VA b0 = gbp[4 * q], b1 = gbp[16 * ROWV + 4 * q];
+#pragma unroll
+      for (int e = 0; e < W; ++e) {
+        const double x0 = a0.get(e), x1 = a1.get(e), y0 = b0.get(e), y1 = b1.get(e);
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
       }
+    }
+    if (more) store_chunk(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  // result tile through LDS (the operand buffers are free after the last barrier):
+  // out[sample][row], row stride 65 doubles
+  double *out = reinterpret_cast<double *>(g16_smem);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) acc[r][g] = __builtin_amdgcn_mfma_f64_4x4x4f64(av[r], bv[g], acc[r][g], 0, 0, 0);
-    }
-    next_chunk();
-  }
-  // Sum the four blocks (lane bits 2-3); every lane of a quadruple adds the
-  // same values in the same pairing, so all four hold the identical total.
-  // Lane (i, b, j) keeps row group rho = b: out[gamma] = D(row 4b + i, sample 4 gamma + j).
-  double out[4];
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    double v[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double x = acc[r][g];
-      x += __shfl_xor(x, 4, 64);
-      x += __shfl_xor(x, 8, 64);
-      v[r] = x;
-    }
-    out[g] = bq == 0 ? v[0] : bq == 1 ? v[1] : bq == 2 ? v[2] : v[3];
-  }
-  if constexpr (KSPLIT > 1) {
-    if (kg > 0) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g) red[(((kg - 1) * 4 + rt) * 64 + lane) * 4 + g] = out[g];
-    }
-    __syncthreads();
-    if (kg > 0) return;
-#pragma unroll
-    for (int h = 1; h < KSPLIT; ++h)
-#pragma unroll
-      for (int g = 0; g < 4; ++g) out[g] += red[(((h - 1) * 4 + rt) * 64 + lane) * 4 + g];
-  }
-  // D row of this lane: 4 b + i with i = lane / 16 (output layout), samples 4 gamma + (lane & 3)
-  const int64_t orow = (int64_t)tl.row0 + rt * 16 + 4 * bq + kq;
+        out[(ws * 32 + b * 16 + li) * (kG16Rows + 1) + wr * 32 + a * 16 + kk + 4 * r] = acc[a][b][r];
+  __syncthreads();
+  const int orl = tid & 63;  // tile row
+  const int64_t orow = (int64_t)tl.row0 + orl;
   if (orow >= rows) return;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const int64_t smp = (int64_t)blockIdx.y * kGemmSamples + 4 * g + lo;
-    if (smp >= samples) continue;
-    if (nd.root)
-      est[(int64_t)nd.net * S + sample0 + smp] = out[g];
+  for (int sl = tid >> 6; sl < kG16Samples; sl += kG16Threads / 64) {
+    const int64_t smp = s_base + sl;
+    if (smp >= samples) break;
+    const double v = out[sl * (kG16Rows + 1) + orl];
+    if (part)
+      part[(((int64_t)blockIdx.z * n_tiles + blockIdx.x) * samples + smp) * kG16Rows + orl] = v;
+    else if (nd.root)
+      est[(int64_t)nd.net * S + sample0 + smp] = v;
     else
-      wbuf[smp * w_row + nd.w_off + orow] = (A)out[g];
+      wbuf[smp * w_row + nd.w_off + orow] = (A)v;
   }
+}
+
+// Roots (one row): y = sum_col X_o[col] g[col] per sample, a dot product bound
+// by the reads of g, on the vector units in FP64.  Block: four waves, 16
+// samples (four per wave); a lane takes the vectors of W columns W lane + 64 W i,
+// then the columns past the last full vector one by one; the wave sums its lanes
+// with a fixed xor tree, so the result does not depend on timing.
+constexpr int kRootSamples = 16;
+
+template <typename T, typename A>
+__global__ __launch_bounds__(256) void m2_root_kernel(const M2Node *__restrict__ nodes,
+                                                      const M2Tile *__restrict__ tiles,
+                                                      const void *const *data, const A *__restrict__ gbuf,
+                                                      int64_t g_row, int64_t samples, double *__restrict__ est,
+                                                      int64_t S, int64_t sample0) {
+  constexpr int W = RawW<T>::W;
+  const M2Node &nd = nodes[tiles[blockIdx.x].node];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t ncols = (int32_t)nd.ncols;
+  const void *X = data[nd.tensor];
+  const bool vec = (reinterpret_cast<uintptr_t>(X) & (uintptr_t)(W * sizeof(T) - 1)) == 0;
+  const int32_t nvec = vec ? ncols / W : 0;  // full vectors; columns from W nvec on are scalar
+  for (int k = 0; k < kRootSamples / 4; ++k) {
+    const int64_t smp = (int64_t)blockIdx.y * kRootSamples + wave * (kRootSamples / 4) + k;
+    if (smp >= samples) break;  // the same in every lane of the wave
+    const A *g = gbuf + smp * g_row + nd.g_off;
+    double acc = 0.0;
+    for (int32_t v = lane; v < nvec; v += 64) {
+      RawW<T> x;
+      RawW<A> y;
+      x.load(X, (int64_t)v * W);
+      y.load(g, (int64_t)v * W);
+#pragma unroll
+      for (int e = 0; e < W; ++e) acc = fma(x.get(e), y.get(e), acc);
+    }
+    for (int32_t col = W * nvec + lane; col < ncols; col += 64)
+      acc = fma(load_val<T>(X, col), (double)g[col], acc);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) est[(int64_t)nd.net * S + sample0 + smp] = acc;
+  }
+}
+
+// Fixed-order sum of the column-split partials of one level.
+template <typename A>
+__global__ __launch_bounds__(256) void m2_reduce_kernel(const M2Node *__restrict__ nodes,
+                                                        const M2Tile *__restrict__ tiles, int32_t n_tiles,
+                                                        int32_t splits, int64_t samples,
+                                                        const double *__restrict__ part,
+                                                        A *__restrict__ wbuf, int64_t w_row,
+                                                        double *__restrict__ est, int64_t S,
+                                                        int64_t sample0) {
+  const M2Tile tl = tiles[blockIdx.x];
+  const M2Node &nd = nodes[tl.node];
+  const int rloc = threadIdx.x & 63;
+  const int64_t smp = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int64_t orow = (int64_t)tl.row0 + rloc;
+  if (smp >= samples || orow >= nd.rows) return;
+  double v = 0.0;
+  for (int z = 0; z < splits; ++z) v += part[(((int64_t)z * n_tiles + blockIdx.x) * samples + smp) * kG16Rows + rloc];
+  if (nd.root)
+    est[(int64_t)nd.net * S + sample0 + smp] = v;
+  else
+    wbuf[smp * w_row + nd.w_off + orow] = (A)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -558,7 +637,8 @@ __global__ __launch_bounds__(256 * KSPLIT) void m2_gemm_kernel(
 // D[i][j] in lane j + 16 (i / 4) item i % 4.  A wave owns 16 rows x 16 samples;
 // lane (i, q) supplies the 8 consecutive columns c0 + 8q .. + 7 of its X row and
 // of its G sample, rounded to BF16 to nearest even; accumulation in FP32.
-// Block and column split as for the FP64 kernel.
+// Block: four waves (64 rows) x 16 samples; KSPLIT groups of four waves take
+// interleaved chunks and are summed in a fixed order in LDS (deterministic).
 typedef __bf16 gbf16x8 __attribute__((ext_vector_type(8)));
 typedef float gf32x4acc __attribute__((ext_vector_type(4)));
 
@@ -716,6 +796,10 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
   M2Plan *P = p->m2;
   const size_t lds = (size_t)p->m * 8 + (size_t)P->tcap * 12;
   auto gk = m2_gather_kernel<T, A>;
+  constexpr size_t g16 = g16_lds_bytes<T, A>();
+  if (g16 > 65536)
+    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
   if (lds > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)gk, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
@@ -733,17 +817,17 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
     if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
-    // Column split: enough waves for four per SIMD (256 CUs x 4), each group of
-    // four waves still taking at least 8 chunks of 32 columns.
-    dim3 g2((unsigned)P->level_tiles[(size_t)d].size(), (unsigned)((n + kGemmSamples - 1) / kGemmSamples));
-    const int64_t waves = 4ll * g2.x * g2.y;
-    int ks = 1;
-    while (ks < 4 && waves * ks < 4096 && P->level_maxcols[(size_t)d] >= 512ll * ks) ks *= 2;
     const void *const *dp = (const void *const *)p->d_data;
     const A *gb = reinterpret_cast<const A *>(P->d_g);
     A *wb = reinterpret_cast<A *>(P->d_w);
     const M2Tile *tl = P->d_level_tiles[(size_t)d];
     if (p->flags & TN_FLAG_MFMA_BF16) {
+      // Column split: enough waves for four per SIMD (256 CUs x 4), each group
+      // of four waves still taking at least 8 chunks of 32 columns.
+      dim3 g2((unsigned)P->level_tiles[(size_t)d].size(), (unsigned)((n + kGemmSamples - 1) / kGemmSamples));
+      const int64_t waves = 4ll * g2.x * g2.y;
+      int ks = 1;
+      while (ks < 4 && waves * ks < 4096 && P->level_maxcols[(size_t)d] >= 512ll * ks) ks *= 2;
       if (ks == 1)
         hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 1>), g2, dim3(256), 0, st, P->d_nodes, tl, dp, gb,
                            P->g_row, n, wb, P->w_row, est, p->S, c0);
@@ -753,15 +837,28 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
       else
         hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 4>), g2, dim3(1024), 0, st, P->d_nodes, tl, dp, gb,
                            P->g_row, n, wb, P->w_row, est, p->S, c0);
-    } else if (ks == 1) {
-      hipLaunchKernelGGL((m2_gemm_kernel<T, A, 1>), g2, dim3(256), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
-                         n, wb, P->w_row, est, p->S, c0);
-    } else if (ks == 2) {
-      hipLaunchKernelGGL((m2_gemm_kernel<T, A, 2>), g2, dim3(512), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
-                         n, wb, P->w_row, est, p->S, c0);
+    } else if (d == 0) {  // roots only, one row each
+      dim3 g3((unsigned)P->level_tiles[0].size(), (unsigned)((n + kRootSamples - 1) / kRootSamples));
+      hipLaunchKernelGGL((m2_root_kernel<T, A>), g3, dim3(256), 0, st, P->d_nodes, tl, dp, gb, P->g_row, n, est,
+                         p->S, c0);
     } else {
-      hipLaunchKernelGGL((m2_gemm_kernel<T, A, 4>), g2, dim3(1024), 0, st, P->d_nodes, tl, dp, gb, P->g_row,
-                         n, wb, P->w_row, est, p->S, c0);
+      const int32_t nt = (int32_t)P->level_tiles[(size_t)d].size();
+      const int32_t z = P->level_splits[(size_t)d];
+      dim3 g4((unsigned)nt, (unsigned)((n + kG16Samples - 1) / kG16Samples), (unsigned)z);
+      double *part = z > 1 ? P->d_part : nullptr;
+      hipLaunchKernelGGL((m2_gemm16_kernel<T, A>), g4, dim3(kG16Threads), g16, st, P->d_nodes,
+                         tl, nt, dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+      TN_HIP_CHECK(hipGetLastError());
+      if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
+      if (z > 1) {  // the partials' sum is timed with the gathers
+        if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+        dim3 g5((unsigned)nt, (unsigned)((n + 3) / 4));
+        hipLaunchKernelGGL((m2_reduce_kernel<A>), g5, dim3(256), 0, st, P->d_nodes, tl, nt, z, n, part, wb,
+                           P->w_row, est, p->S, c0);
+        TN_HIP_CHECK(hipGetLastError());
+        if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
+      }
+      continue;
     }
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
@@ -881,9 +978,9 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
         nd.child_dim[i] = (int32_t)n.dims[u];
         nd.ncols *= n.dims[u];
         dsum += n.dims[u];
-        if (nd.ncols > 0x7fffffffll)
+        if (nd.ncols > 0x7fff0000ll)  // 32-bit column arithmetic with a chunk of headroom
           return set_error(TN_ERR_UNSUPPORTED,
-                           "acyclic method: network %d tensor %d: more than 2^31 child index tuples", j, k);
+                           "acyclic method: network %d tensor %d: more than 2^31 - 2^16 child index tuples", j, k);
         const int e = c.edge_of[(size_t)u];
         nd.child_edge[i] = e;
         nd.child_tab[i] = edge_tab[(size_t)e];
@@ -989,6 +1086,26 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   P->chunk = chunk;
   p->chunk = chunk;
   p->sb = 1;
+  // Column split of the FP64 products: a level with few 64 x 64 tiles spreads
+  // its columns over up to 8 blocks per tile, towards 512 blocks (two per CU),
+  // each range still at least 8 chunks of 16 W columns.  The partials buffer,
+  // [splits][tiles][chunk][64] doubles, then stays below 1024 x 64 x 64 x 8 B.
+  const int64_t cc = p->dtype == TN_F64 ? 32 : 64;
+  size_t part = 0;
+  P->level_splits.assign(P->level_tiles.size(), 1);
+  P->level_kcols.assign(P->level_tiles.size(), 0);
+  for (size_t d = 0; d < P->level_tiles.size(); ++d) {
+    const int64_t tiles = (int64_t)P->level_tiles[d].size();
+    if (tiles == 0) continue;
+    const int64_t blocks = tiles * ((chunk + kG16Samples - 1) / kG16Samples);
+    const int64_t maxc = P->level_maxcols[d];
+    int32_t z = 1;
+    while (z < 8 && blocks * z < 512 && maxc >= 16 * cc * z) z *= 2;
+    const int64_t kc = ((maxc + z - 1) / z + cc - 1) / cc * cc;
+    P->level_splits[d] = z;
+    P->level_kcols[d] = (int32_t)kc;
+    if (z > 1) part = std::max(part, (size_t)z * (size_t)tiles * (size_t)chunk * kG16Rows);
+  }
   int rc;
   if ((rc = upload_vec(&p->d_streams, p->h_streams)) != TN_OK) return rc;
   if ((rc = upload_vec(&P->d_nodes, P->h_nodes)) != TN_OK) return rc;
@@ -1014,6 +1131,9 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   void *r = nullptr;
   if ((rc = alloc(&r, (size_t)chunk * (size_t)p->n_nets * (size_t)p->m * 8)) != TN_OK) return rc;
   P->d_r = reinterpret_cast<double *>(r);
+  void *q = nullptr;
+  if ((rc = alloc(&q, part * 8)) != TN_OK) return rc;
+  P->d_part = reinterpret_cast<double *>(q);
   return TN_OK;
 }
 
@@ -1055,6 +1175,7 @@ void m2_release(tn_plan *p) {
   if (P->d_g) (void)hipFree(P->d_g);
   if (P->d_w) (void)hipFree(P->d_w);
   if (P->d_r) (void)hipFree(P->d_r);
+  if (P->d_part) (void)hipFree(P->d_part);
   delete P;
   p->m2 = nullptr;
 }
