@@ -156,6 +156,26 @@ def measured_traffic(workload_name, samples_per_pass, kernel_sources):
     return None, None
 
 
+def kernel_breakdown(T, specs, meth, m, S, flags, steps):
+    """Device ms per step of each kernel kind, from a separate untimed pass of
+    `steps` estimates with HIP events around every launch."""
+    import torch
+    plan = T.Plan(specs, meth, m, S, 0, flags=flags)
+    stats = torch.empty(2 * len(specs), dtype=torch.float64, device="cuda")
+    plan.estimate(stats)
+    torch.cuda.synchronize()
+    kinds = {"sketch": T.TN_KERNEL_SKETCH, "hash": T.TN_KERNEL_HASH, "combine": T.TN_KERNEL_COMBINE,
+             "stats": T.TN_KERNEL_STATS}
+    for k in kinds.values():
+        plan.kernel_time(k)
+    for _ in range(steps):
+        plan.estimate(stats)
+    torch.cuda.synchronize()
+    out = {name: plan.kernel_time(k)[0] / steps for name, k in kinds.items()}
+    plan.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -175,7 +195,10 @@ def main():
         ts = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda", td) for x in n.data]
         specs.append(T.NetworkSpec.from_network(n, ts))
     torch.cuda.synchronize()
-    flags = T.TN_FLAG_PROFILE | (0 if os.environ.get("TN_SCATTER_SB") else T.TN_FLAG_AUTOTUNE)
+    # Timed region: HIP events around the sketching launches only (each event
+    # costs device time); the per-kind breakdown comes from a second pass below.
+    base_flags = 0 if os.environ.get("TN_SCATTER_SB") else T.TN_FLAG_AUTOTUNE
+    flags = base_flags | T.TN_FLAG_PROFILE | T.TN_FLAG_PROFILE_SKETCH
     bf16_products = a.products == "bf16" and method == "acyclic"
     if bf16_products:
         flags |= T.TN_FLAG_MFMA_BF16
@@ -198,9 +221,8 @@ def main():
     ms_step = wall * 1e3 / a.steps
     value = len(nets) * S * a.steps / wall
     sk_ms, sk_n = plan.kernel_time(T.TN_KERNEL_SKETCH)
-    kt = {"hash": plan.kernel_time(T.TN_KERNEL_HASH), "combine": plan.kernel_time(T.TN_KERNEL_COMBINE),
-          "stats": plan.kernel_time(T.TN_KERNEL_STATS)}
     avg_ms = sk_ms / max(1, sk_n)
+    kt = kernel_breakdown(T, specs, meth, m, S, (flags & ~T.TN_FLAG_PROFILE_SKETCH), a.steps)
     entries = sum(n.nnz() for n in nets)
     esize = np.dtype(dtype).itemsize
     if method == "cyclic":
@@ -261,7 +283,7 @@ def main():
         "at_1e-2": {"median_input_relative_std": float(np.median(rel_std)),
                     "median_samples_needed": float(np.median(need)),
                     "networks_per_s": float(len(nets) / np.sum(need) * value)},
-        "kernel_ms_per_step": {"sketch": sk_ms / a.steps, **{k: v[0] / a.steps for k, v in kt.items()}},
+        "kernel_ms_per_step": kt,
     }
     plan.close()
     if not a.no_cpu_baseline:

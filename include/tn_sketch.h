@@ -97,6 +97,11 @@ extern "C" {
                                    up to FP rounding of the combine (TN_ERR_UNSUPPORTED with
                                    TN_ACYCLIC) */
 
+#define TN_FLAG_PROFILE_SKETCH 0x20u /* with TN_FLAG_PROFILE: record the events around the
+                                   TN_KERNEL_SKETCH launches only (each recorded event costs a
+                                   few microseconds of device time; the other kinds then read
+                                   0 launches).  TN_ERR_ARG without TN_FLAG_PROFILE */
+
 /* Kernel kinds for tn_plan_kernel_time. */
 #define TN_KERNEL_HASH 0        /* count-sketch table generation */
 #define TN_KERNEL_SKETCH 1      /* sketching pass: cyclic scatter / acyclic leaf+SMVP sweep */

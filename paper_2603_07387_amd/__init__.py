@@ -10,7 +10,7 @@ fallback path.
 from ._binding import (  # noqa: F401
     TN_OK, TN_ERR_ARG, TN_ERR_DIMS, TN_ERR_HYPEREDGE, TN_ERR_SELFLOOP, TN_ERR_CYCLIC,
     TN_ERR_PARTIAL, TN_ERR_OOM, TN_ERR_HIP, TN_ERR_UNSUPPORTED, TN_F64, TN_F32, TN_BF16,
-    TN_CYCLIC, TN_ACYCLIC, TN_FLAG_GRAPH, TN_FLAG_PROFILE, TN_FLAG_AUTOTUNE, TN_FLAG_MFMA_BF16, TN_FLAG_PERSISTENT, TN_KERNEL_HASH, TN_KERNEL_SKETCH,
+    TN_CYCLIC, TN_ACYCLIC, TN_FLAG_GRAPH, TN_FLAG_PROFILE, TN_FLAG_AUTOTUNE, TN_FLAG_MFMA_BF16, TN_FLAG_PERSISTENT, TN_FLAG_PROFILE_SKETCH, TN_KERNEL_HASH, TN_KERNEL_SKETCH,
     TN_KERNEL_COMBINE, TN_KERNEL_STATS, TNError, NetworkSpec, Plan, lib_path, load,
     tn_sketch_plan, tn_sketch_estimate, tn_contract_exact, tn_plan_destroy, tn_last_error,
     tn_plan_query, tn_plan_stream, tn_plan_get_hashes, tn_plan_set_hashes, tn_plan_get_sketches,

@@ -28,6 +28,7 @@ TN_FLAG_PROFILE = 0x2
 TN_FLAG_AUTOTUNE = 0x4
 TN_FLAG_MFMA_BF16 = 0x8
 TN_FLAG_PERSISTENT = 0x10
+TN_FLAG_PROFILE_SKETCH = 0x20
 TN_KERNEL_HASH, TN_KERNEL_SKETCH, TN_KERNEL_COMBINE, TN_KERNEL_STATS = 0, 1, 2, 3
 
 _DTYPES = {torch.float64: TN_F64, torch.float32: TN_F32, torch.bfloat16: TN_BF16}

@@ -125,8 +125,10 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
   if (m < 1 || (m & (m - 1)) != 0) return set_error(TN_ERR_ARG, "m = %lld is not a power of two", (long long)m);
   if (method != TN_CYCLIC && method != TN_ACYCLIC) return set_error(TN_ERR_ARG, "method %d", method);
   if (flags & ~(uint32_t)(TN_FLAG_GRAPH | TN_FLAG_PROFILE | TN_FLAG_AUTOTUNE | TN_FLAG_MFMA_BF16 |
-                          TN_FLAG_PERSISTENT))
+                          TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH))
     return set_error(TN_ERR_ARG, "unknown flags 0x%x", flags);
+  if ((flags & TN_FLAG_PROFILE_SKETCH) && !(flags & TN_FLAG_PROFILE))
+    return set_error(TN_ERR_ARG, "TN_FLAG_PROFILE_SKETCH needs TN_FLAG_PROFILE");
   if ((flags & TN_FLAG_PERSISTENT) && method != TN_CYCLIC)
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_PERSISTENT applies to the cyclic method");
   if ((flags & TN_FLAG_MFMA_BF16) && method != TN_ACYCLIC)

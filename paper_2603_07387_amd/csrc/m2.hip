@@ -228,6 +228,50 @@ __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const in
   }
 }
 
+// Two children with the faster one of at most 256 values (the usual shape: a
+// bond and a physical leg).  Thread t keeps i1 = t mod d1 for the whole pass and
+// walks i0 = t / d1 + R k, R = floor(256 / d1), so the second child's table
+// entry and w value stay in registers and a wave reads the first child's by
+// broadcast; columns are i0 d1 + i1 as in gather_columns.  The sign of a column
+// is folded into the product before the fixed-point conversion: fma rounds
+// +x and -x symmetrically, so every sketch entry and every g value is bitwise
+// that of gather_columns<A, 2>.
+template <typename A>
+__device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab_base, const uint32_t *dtab,
+                                            const double *wv, unsigned long long *acc, uint32_t mask, double sc,
+                                            double inv_sc, A *g) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t d0 = (uint32_t)nd.child_dim[0], d1 = (uint32_t)nd.child_dim[1];
+  const uint32_t R = 256u / d1;
+  const bool active = tid < R * d1;
+  const uint32_t i1 = tid % d1, i0s = tid / d1;
+  const uint32_t *t0 = dtab + tab_base[0];
+  const double *w0 = wv + tab_base[0];
+  const uint32_t v1 = active ? dtab[tab_base[1] + (int32_t)i1] : 0u;
+  const uint32_t v1m = v1 & 0x7fffffffu;
+  const double w1 = active ? wv[tab_base[1] + (int32_t)i1] : 0.0;
+  const double kMagic = 6755399441055744.0;
+  const long long kMagicBits = __double_as_longlong(kMagic);
+  if (active) {
+    for (uint32_t i0 = i0s; i0 < d0; i0 += R) {
+      const uint32_t v0 = t0[i0];
+      const uint32_t b = ((v0 & 0x7fffffffu) + v1m) & mask;
+      const long long sg = (long long)((v0 ^ v1) & 0x80000000u) << 32;
+      const double p = __longlong_as_double(__double_as_longlong(w0[i0] * w1) ^ sg);
+      atomicAdd(&acc[b], (unsigned long long)(__double_as_longlong(fma(p, sc, kMagic)) - kMagicBits));
+    }
+  }
+  __syncthreads();
+  if (active) {
+    for (uint32_t i0 = i0s; i0 < d0; i0 += R) {
+      const uint32_t v0 = t0[i0];
+      const uint32_t b = ((v0 & 0x7fffffffu) + v1m) & mask;
+      const A r = (A)((double)(long long)acc[b] * inv_sc);
+      g[(size_t)i0 * d1 + i1] = ((v0 ^ v1) & 0x80000000u) ? -r : r;
+    }
+  }
+}
+
 // One sample's sketch r_k and gather g for tensor k (see the file comment).
 // A: storage type of w and g (float for FP32/BF16 data, double for FP64).
 template <typename T, typename A>
@@ -334,7 +378,12 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
   A *g = gbuf + s * g_row + nd.g_off;
   switch (qt) {
     case 1: gather_columns<A, 1>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
-    case 2: gather_columns<A, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+    case 2:
+      if (nd.child_dim[1] <= 256)
+        gather_pair<A>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
+      else
+        gather_columns<A, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g);
+      break;
     case 4: gather_columns<A, 4>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
     default: gather_columns<A, 8>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
   }
@@ -807,7 +856,7 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     if (P->level_nodes[(size_t)d].empty()) continue;
     hipEvent_t ev = nullptr;
     int rc;
-    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
     dim3 g1((unsigned)P->level_nodes[(size_t)d].size(), (unsigned)n);
     hipLaunchKernelGGL(gk, g1, dim3(256), lds, st, P->d_nodes, P->d_level_nodes[(size_t)d],
                        (const void *const *)p->d_data, tables, p->W, c0, p->log2m,
@@ -816,7 +865,7 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
                        export_out ? P->d_r : nullptr, (int64_t)p->n_nets * p->m, P->tcap);
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
-    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = prof_begin(p, st, &ev, TN_KERNEL_SKETCH)) != TN_OK) return rc;
     const void *const *dp = (const void *const *)p->d_data;
     const A *gb = reinterpret_cast<const A *>(P->d_g);
     A *wb = reinterpret_cast<A *>(P->d_w);
@@ -851,7 +900,7 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
       TN_HIP_CHECK(hipGetLastError());
       if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
       if (z > 1) {  // the partials' sum is timed with the gathers
-        if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+        if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
         dim3 g5((unsigned)nt, (unsigned)((n + 3) / 4));
         hipLaunchKernelGGL((m2_reduce_kernel<A>), g5, dim3(256), 0, st, P->d_nodes, tl, nt, z, n, part, wb,
                            P->w_row, est, p->S, c0);

@@ -127,7 +127,7 @@ int plan_set_hashes(tn_plan *p, const int32_t *tables, hipStream_t st);
 int plan_get_sketches(tn_plan *p, const tn_network *nets, int64_t first, int64_t count,
                       hipStream_t st, double *out);
 int plan_bind(tn_plan *p, const tn_network *nets, hipStream_t st);
-int prof_begin(tn_plan *p, hipStream_t st, hipEvent_t *ev);
+int prof_begin(tn_plan *p, hipStream_t st, hipEvent_t *ev, int kind);
 int prof_end(tn_plan *p, hipStream_t st, int kind, hipEvent_t start);
 int plan_kernel_time(tn_plan *p, int kind, double *ms, int64_t *launches);
 

@@ -261,7 +261,7 @@ int m1_tables(tn_plan *p, int64_t c0, int64_t n, hipStream_t st, const int32_t *
   }
   *tables = p->d_tables;
   hipEvent_t ev = nullptr;
-  int rc = prof_begin(p, st, &ev);
+  int rc = prof_begin(p, st, &ev, TN_KERNEL_HASH);
   if (rc == TN_OK)
     rc = launch_hashgen(p->d_streams, (int64_t)p->h_streams.size(), p->W, c0, n, p->m,
                         p->d_tables, st);
@@ -300,7 +300,7 @@ int m1_run_fused(tn_plan *p, hipStream_t st, double *est) {
     L.twiddles = p->d_tw;
     L.est = est;
     hipEvent_t ev = nullptr;
-    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = prof_begin(p, st, &ev, TN_KERNEL_SKETCH)) != TN_OK) return rc;
     if ((rc = launch_m1_fused(L, st)) != TN_OK) return rc;
     if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
   }
@@ -329,10 +329,10 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
     L.lds_bytes = p->scatter_lds;
     L.ybuf = p->d_ybuf;
     hipEvent_t ev = nullptr;
-    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = prof_begin(p, st, &ev, TN_KERNEL_SKETCH)) != TN_OK) return rc;
     if ((rc = launch_m1_scatter(L, st)) != TN_OK) return rc;
     if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
-    if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+    if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
     if ((rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf,
                                 (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, est,
                                 st)) != TN_OK)
@@ -377,8 +377,8 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
   int rc = m1_tables(p, 0, n, st, &tables);
   if (rc != TN_OK) return rc;
   hipEvent_t e0, e1;
-  TN_HIP_CHECK(hipEventCreate(&e0));
-  TN_HIP_CHECK(hipEventCreate(&e1));
+  TN_HIP_CHECK(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  TN_HIP_CHECK(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   std::pair<int, int> best{p->fused ? p->fused_sb : p->sb, p->fused ? p->fused_banks : p->banks};
   float best_ms = 1e30f;
   const int sbs_slot[] = {1, 2, 4, 8, 16}, sbs_fused[] = {1, 2, 4};
@@ -467,19 +467,22 @@ int run_all(tn_plan *p, hipStream_t st, double *stats, double *est) {
   int rc = (p->method == TN_CYCLIC) ? m1_run(p, st, est) : m2_estimate(p, st, est);
   if (rc != TN_OK) return rc;
   hipEvent_t ev = nullptr;
-  if ((rc = prof_begin(p, st, &ev)) != TN_OK) return rc;
+  if ((rc = prof_begin(p, st, &ev, TN_KERNEL_STATS)) != TN_OK) return rc;
   if ((rc = launch_sample_stats(est, p->n_nets, p->S, stats, st)) != TN_OK) return rc;
   return prof_end(p, st, TN_KERNEL_STATS, ev);
 }
 
 }  // namespace
 
-int prof_begin(tn_plan *p, hipStream_t st, hipEvent_t *ev) {
+// Timing events carry no system-scope fence: they only time kernels, and a
+// fence per record (a cache write-back) would slow the work being timed.
+int prof_begin(tn_plan *p, hipStream_t st, hipEvent_t *ev, int kind) {
   *ev = nullptr;
   if (!(p->flags & TN_FLAG_PROFILE)) return TN_OK;
+  if ((p->flags & TN_FLAG_PROFILE_SKETCH) && kind != TN_KERNEL_SKETCH) return TN_OK;
   if (p->prof_pool.empty()) {
     hipEvent_t e;
-    TN_HIP_CHECK(hipEventCreate(&e));
+    TN_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     p->prof_pool.push_back(e);
   }
   *ev = p->prof_pool.back();
@@ -492,7 +495,7 @@ int prof_end(tn_plan *p, hipStream_t st, int kind, hipEvent_t start) {
   if (!(p->flags & TN_FLAG_PROFILE) || !start) return TN_OK;
   if (p->prof_pool.empty()) {
     hipEvent_t e;
-    TN_HIP_CHECK(hipEventCreate(&e));
+    TN_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     p->prof_pool.push_back(e);
   }
   hipEvent_t stop = p->prof_pool.back();

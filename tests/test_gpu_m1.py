@@ -288,3 +288,22 @@ def test_exact_contraction(T, orc):
         ref = orc.tc_full(v)
         scale = np.prod([np.abs(x).sum() for x in v.data])
         assert abs(got - ref) <= 1e-12 * scale + 1e-12 * abs(ref), (net.name, got, ref)
+
+
+def test_profile_sketch_only(T, orc):
+    """TN_FLAG_PROFILE_SKETCH records events around the sketching launches only;
+    the estimates are those of an unprofiled plan; without TN_FLAG_PROFILE it
+    is rejected."""
+    nets = [W.triangle(16, seed=2), W.ring(5, 12, seed=4)]
+    base, _ = make_plan(T, nets, "float32", 256, 6, 8)
+    prof, _ = make_plan(T, nets, "float32", 256, 6, 8, flags=T.TN_FLAG_PROFILE | T.TN_FLAG_PROFILE_SKETCH)
+    _, g0 = run(base)
+    _, g1 = run(prof)
+    assert np.array_equal(g0, g1)
+    ms, n = prof.kernel_time(T.TN_KERNEL_SKETCH)
+    assert n > 0 and ms > 0.0
+    for k in (T.TN_KERNEL_HASH, T.TN_KERNEL_COMBINE, T.TN_KERNEL_STATS):
+        assert prof.kernel_time(k) == (0.0, 0)
+    with pytest.raises(T.TNError) as e:
+        make_plan(T, nets, "float32", 256, 6, 8, flags=T.TN_FLAG_PROFILE_SKETCH)
+    assert e.value.code == T.TN_ERR_ARG

@@ -132,6 +132,17 @@ def test_padding_three_and_five_children(T, orc):
     check(orc, plan, views, 21, "float64")
 
 
+@pytest.mark.parametrize("bond", [100, 300])
+def test_two_child_gather_paths(T, orc, bond):
+    """Tensors with two children take the register-held second child when its
+    dimension is at most 256 (bond 100: 2 index rows per pass, 56 idle threads)
+    and the general mixed-radix walk otherwise (bond 300)."""
+    net = W.tt_caterpillar(cores=3, bond=bond, phys=3, seed=4, dtype=np.float64)
+    for dtype in ("float64", "float32"):
+        plan, views = make_plan(T, [net], dtype, 512, 4, 17)
+        check(orc, plan, views, 17, dtype)
+
+
 def test_caterpillar_full_size(T, orc):
     """Tensor-train cores (1,64,64), (64,64,64) x 30, (64,64,1) with their physical
     legs contracted against vectors, N(0, 1/64), m = 4096; sampled seeds."""
