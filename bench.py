@@ -156,6 +156,32 @@ def measured_traffic(workload_name, samples_per_pass, kernel_sources):
     return None, None
 
 
+def m2_products(net, root=0):
+    """(rows, cols) of w_k = mat(X_k) G for every tensor with children when the
+    tree is rooted at `root`: rows is the size of the parent mode (1 at the
+    root), cols the product of the child modes."""
+    import numpy as np
+    owner = [k for k in range(net.p) for _ in range(net.orders[k])]
+    partner = {}
+    for (u, v) in net.edges:
+        partner[u], partner[v] = v, u
+    parent_mode = {root: None}
+    order = [root]
+    for k in order:
+        for u in net.modes(k):
+            l = owner[partner[u]]
+            if u != parent_mode[k] and l not in parent_mode:
+                parent_mode[l] = partner[u]
+                order.append(l)
+    out = []
+    for k in range(net.p):
+        rows = 1 if parent_mode[k] is None else net.dims[parent_mode[k]]
+        cols = int(np.prod([net.dims[u] for u in net.modes(k) if u != parent_mode[k]], dtype=np.int64))
+        if net.orders[k] > (0 if parent_mode[k] is None else 1):
+            out.append((rows, cols))
+    return out
+
+
 def kernel_breakdown(T, specs, meth, m, S, flags, steps):
     """Device ms per step of each kernel kind, from a separate untimed pass of
     `steps` estimates with HIP events around every launch."""
@@ -245,17 +271,24 @@ def main():
                 "avg_launch_ms": avg_ms, "launches": sk_n, "algorithmic_bytes_per_launch": launch_units,
                 "samples_per_pass": sb, "accumulator_banks": banks}
     else:
-        # One GEMM launch per tree depth on the FP64 matrix cores: 2 * rows *
-        # cols * samples flops of w_k = mat(X_k) G for every tensor with
-        # children at that depth.
-        flops_step = 2.0 * sum((n.nnz() - sum(int(np.prod(n.shape(k))) for k in range(n.p)
-                                               if len(n.shape(k)) == 1 and k != 0)) for n in nets) * S
-        achieved = flops_step / (sk_ms / a.steps * 1e-3) / 1e12
-        peak = BF16_MFMA_PEAK_TFLOPS if bf16_products else FP64_MFMA_PEAK_TFLOPS
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
-                "kernel": "m2_gemm_bf16_kernel" if bf16_products else "m2_gemm16_kernel",
-                "avg_launch_ms": avg_ms, "launches": sk_n, "flops_per_step": flops_step}
+        # One product launch per tree depth: w_k = mat(X_k) G for every tensor
+        # with children, rows x cols times cols x S.
+        prods = [rc for n in nets for rc in m2_products(n)]
+        flops_step = 2.0 * sum(r * c for r, c in prods) * S
+        if bf16_products:
+            # BF16 matrix cores are ~30x faster than the FP64 ones: the launch is
+            # bound by reading G (FP32, cols x S), X once and writing w.
+            bytes_step = sum(S * c * 4 + r * c * esize + S * r * 4 for r, c in prods)
+            achieved = bytes_step / (sk_ms / a.steps * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "m2_gemm16_kernel<BF16>",
+                    "avg_launch_ms": avg_ms, "launches": sk_n, "algorithmic_bytes_per_step": bytes_step,
+                    "flops_per_step": flops_step}
+        else:
+            achieved = flops_step / (sk_ms / a.steps * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None, "kernel": "m2_gemm16_kernel",
+                    "avg_launch_ms": avg_ms, "launches": sk_n, "flops_per_step": flops_step}
     st = stats.cpu().numpy().reshape(-1, 2)
     norms = np.array([n.input_norm() for n in nets])
     # input-relative std of one estimate (Def. 4's error scale), and the samples

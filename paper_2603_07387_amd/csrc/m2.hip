@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <new>
 #include <queue>
+#include <type_traits>
 #include <vector>
 
 #include "hash_device.h"
@@ -398,6 +399,8 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
 typedef float gf32x4 __attribute__((ext_vector_type(4)));
 typedef double gf64x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short gu16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 gbf16x8 __attribute__((ext_vector_type(8)));
+typedef float gf32x4acc __attribute__((ext_vector_type(4)));
 #define TN_GLOBAL __attribute__((address_space(1)))
 
 // W consecutive values as loaded (16 B of FP32, 8 B of BF16, 16 B of FP64),
@@ -441,12 +444,14 @@ struct RawW<uint16_t> {
   __device__ __forceinline__ double get(int i) const { return (double)__uint_as_float((uint32_t)v[i] << 16); }
 };
 
-constexpr int kGemmRows = 64;     // rows per block (four waves of 16)
-constexpr int kGemmSamples = 16;  // samples per block
 
 // ---------------------------------------------------------------------------
-// The FP64 product on v_mfma_f64_16x16x4f64 (A[i][k] in lane i + 16k, B[k][j] in
-// lane j + 16k, D[i][j] as element i / 4 of lane j + 16 (i % 4)).  A block of four
+// The product on v_mfma_f64_16x16x4f64 (A[i][k] in lane i + 16k, B[k][j] in
+// lane j + 16k, D[i][j] as element i / 4 of lane j + 16 (i % 4)); with BF
+// (TN_FLAG_MFMA_BF16) on v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i + 16 (k / 8)
+// element k % 8, B[k][j] in lane j + 16 (k / 8) element k % 8, D[i][j] in lane
+// j + 16 (i / 4) item i % 4), operands rounded to BF16, FP32 accumulation, the
+// same staging, partials and reduction in FP64.  A block of four
 // waves owns 64 rows x 64 samples and a column range; each wave a 32 x 32 corner
 // (2 x 2 accumulators of 16 x 16).  Per chunk of 16 W columns the block stages the
 // X rows and the G rows in double-buffered LDS, one 16-byte vector (W columns) per
@@ -465,7 +470,7 @@ constexpr size_t g16_lds_bytes() {
   return tiles > outb ? tiles : outb;
 }
 
-template <typename T, typename A>
+template <typename T, typename A, bool BF>
 __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, int32_t n_tiles,
     const void *const *data, const A *__restrict__ gbuf, int64_t g_row, int64_t samples,
@@ -552,11 +557,12 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     }
   };
   typedef double d4 __attribute__((ext_vector_type(4)));
-  d4 acc[2][2];
+  using Acc = typename std::conditional<BF, gf32x4acc, d4>::type;
+  Acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = Acc{0, 0, 0, 0};
   int buf = 0;
   if (c_begin < c_end) {
     load_chunk();
@@ -571,17 +577,47 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     }
     const V *xb = Xs + ((size_t)buf * kG16Rows + wr * 32 + li) * ROWV + kk;
     const VA *gbp = Gs + ((size_t)buf * kG16Samples + ws * 32 + li) * ROWV + kk;
+    if constexpr (BF) {
+      // k-step st of 32 columns: lane (i, kk) packs its 8 / W vectors
+      // kk + 4 (v + (8 / W) st), W values each, as elements 0..7 (contraction
+      // index 8 kk + element), rounded to BF16 to nearest even via FP32.
+      constexpr int NV = 8 / W;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const V a0 = xb[4 * q], a1 = xb[16 * ROWV + 4 * q];
-      const VA b0 = gbp[4 * q], b1 = gbp[16 * ROWV + 4 * q];
+      for (int st = 0; st < W / 2; ++st) {
+        gbf16x8 xa[2], gv[2];
 #pragma unroll
-      for (int e = 0; e < W; ++e) {
-        const double x0 = a0.get(e), x1 = a1.get(e), y0 = b0.get(e), y1 = b1.get(e);
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+        for (int v = 0; v < NV; ++v) {
+          const int slot = 4 * (v + NV * st);
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const V xv = xb[16 * ROWV * h + slot];
+            const VA yv = gbp[16 * ROWV * h + slot];
+#pragma unroll
+            for (int e = 0; e < W; ++e) {
+              xa[h][v * W + e] = (__bf16)(float)xv.get(e);
+              gv[h][v * W + e] = (__bf16)(float)yv.get(e);
+            }
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[a], gv[b], acc[a][b], 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const V a0 = xb[4 * q], a1 = xb[16 * ROWV + 4 * q];
+        const VA b0 = gbp[4 * q], b1 = gbp[16 * ROWV + 4 * q];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          const double x0 = a0.get(e), x1 = a1.get(e), y0 = b0.get(e), y1 = b1.get(e);
+          acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[1][1], 0, 0, 0);
+        }
       }
     }
     if (more) store_chunk(buf ^ 1);
@@ -597,7 +633,8 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[(ws * 32 + b * 16 + li) * (kG16Rows + 1) + wr * 32 + a * 16 + kk + 4 * r] = acc[a][b][r];
+        out[(ws * 32 + b * 16 + li) * (kG16Rows + 1) + wr * 32 + a * 16 + (BF ? 4 * kk + r : kk + 4 * r)] =
+            (double)acc[a][b][r];
   __syncthreads();
   const int orl = tid & 63;  // tile row
   const int64_t orow = (int64_t)tl.row0 + orl;
@@ -679,135 +716,6 @@ __global__ __launch_bounds__(256) void m2_reduce_kernel(const M2Node *__restrict
     wbuf[smp * w_row + nd.w_off + orow] = (A)v;
 }
 
-// ---------------------------------------------------------------------------
-// The same product on the BF16 matrix cores (TN_FLAG_MFMA_BF16):
-// v_mfma_f32_16x16x32_bf16, lane layout (measured) A[i][k] in lane
-// i + 16 (k / 8) element k % 8, B[k][j] in lane j + 16 (k / 8) element k % 8,
-// D[i][j] in lane j + 16 (i / 4) item i % 4.  A wave owns 16 rows x 16 samples;
-// lane (i, q) supplies the 8 consecutive columns c0 + 8q .. + 7 of its X row and
-// of its G sample, rounded to BF16 to nearest even; accumulation in FP32.
-// Block: four waves (64 rows) x 16 samples; KSPLIT groups of four waves take
-// interleaved chunks and are summed in a fixed order in LDS (deterministic).
-typedef __bf16 gbf16x8 __attribute__((ext_vector_type(8)));
-typedef float gf32x4acc __attribute__((ext_vector_type(4)));
-
-// Eight consecutive values from `base + off` as FP32 (vector path: aligned and
-// in one contiguous run).
-template <typename T>
-__device__ __forceinline__ void load8(const void *base, int64_t off, float *v);
-template <>
-__device__ __forceinline__ void load8<float>(const void *base, int64_t off, float *v) {
-  const TN_GLOBAL gf32x4 *q = (const TN_GLOBAL gf32x4 *)(reinterpret_cast<const float *>(base) + off);
-  const gf32x4 a = q[0], b = q[1];
-  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-}
-template <>
-__device__ __forceinline__ void load8<double>(const void *base, int64_t off, float *v) {
-  const TN_GLOBAL gf64x2 *q = (const TN_GLOBAL gf64x2 *)(reinterpret_cast<const double *>(base) + off);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const gf64x2 a = q[i];
-    v[2 * i] = (float)a.x;
-    v[2 * i + 1] = (float)a.y;
-  }
-}
-template <>
-__device__ __forceinline__ void load8<uint16_t>(const void *base, int64_t off, float *v) {
-  const TN_GLOBAL gu16x4 *q = (const TN_GLOBAL gu16x4 *)(reinterpret_cast<const uint16_t *>(base) + off);
-  const gu16x4 a = q[0], b = q[1];
-  v[0] = __uint_as_float((uint32_t)a.x << 16); v[1] = __uint_as_float((uint32_t)a.y << 16);
-  v[2] = __uint_as_float((uint32_t)a.z << 16); v[3] = __uint_as_float((uint32_t)a.w << 16);
-  v[4] = __uint_as_float((uint32_t)b.x << 16); v[5] = __uint_as_float((uint32_t)b.y << 16);
-  v[6] = __uint_as_float((uint32_t)b.z << 16); v[7] = __uint_as_float((uint32_t)b.w << 16);
-}
-template <typename T>
-__device__ __forceinline__ float load1f(const void *base, int64_t off) {
-  return (float)load_val<T>(base, off);
-}
-
-template <typename T, typename A, int KSPLIT>
-__global__ __launch_bounds__(256 * KSPLIT) void m2_gemm_bf16_kernel(
-    const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, const void *const *data,
-    const A *__restrict__ gbuf, int64_t g_row, int64_t samples, A *__restrict__ wbuf,
-    int64_t w_row, double *__restrict__ est, int64_t S, int64_t sample0) {
-  constexpr int32_t kChunk = 32;
-  constexpr int32_t kStep = kChunk * KSPLIT;
-  __shared__ gf32x4acc red[KSPLIT > 1 ? (KSPLIT - 1) * 256 : 1];
-  const M2Tile tl = tiles[blockIdx.x];
-  const M2Node &nd = nodes[tl.node];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int rt = wave & 3, kg = wave >> 2;
-  const int li = lane & 15, q = lane >> 4;
-  const int64_t rows = nd.rows, after = nd.after;
-  const int32_t ncols = (int32_t)nd.ncols;
-  const int64_t row = (int64_t)tl.row0 + rt * 16 + li;
-  const int64_t smp = (int64_t)blockIdx.y * kGemmSamples + li;
-  const bool row_ok = row < rows, smp_ok = smp < samples;
-  const void *X = data[nd.tensor];
-  const A *grow = gbuf + (smp_ok ? smp : 0) * g_row + nd.g_off;
-  // eight consecutive columns in one contiguous run, and alignment (rows of g
-  // start at multiples of 4 elements by construction)
-  const bool vec_x = (after % 8) == 0 &&
-                     (reinterpret_cast<uintptr_t>(X) & (uintptr_t)(4 * sizeof(T) - 1)) == 0;
-  const bool vec_g = ((nd.g_off | g_row) & 3) == 0;
-  int32_t c = kg * kChunk + 8 * q;
-  const int32_t after32 = (int32_t)after;
-  int32_t qd = c / after32, rm = c - qd * after32;
-  const int32_t stepq = kStep / after32, stepr = kStep - stepq * after32;
-  gf32x4acc acc = {0.f, 0.f, 0.f, 0.f};
-  for (int32_t cb = kg * kChunk; cb < ncols; cb += kStep) {
-    float xv[8], gv[8];
-    const bool full = c + 7 < ncols;
-    if (full && vec_x && row_ok) {
-      load8<T>(X, ((int64_t)qd * rows + row) * after + rm, xv);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int32_t ce = c + e;
-        float v = 0.f;
-        if (row_ok && ce < ncols) {
-          const int32_t qe = ce / after32;
-          v = load1f<T>(X, ((int64_t)qe * rows + row) * after + (ce - qe * after32));
-        }
-        xv[e] = v;
-      }
-    }
-    if (full && vec_g && smp_ok) {
-      load8<A>(grow, c, gv);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) gv[e] = (smp_ok && c + e < ncols) ? (float)grow[c + e] : 0.f;
-    }
-    gbf16x8 xa, gb;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      xa[e] = (__bf16)xv[e];
-      gb[e] = (__bf16)gv[e];
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa, gb, acc, 0, 0, 0);
-    c += kStep;
-    qd += stepq;
-    rm += stepr;
-    if (rm >= after32) { rm -= after32; ++qd; }
-  }
-  if constexpr (KSPLIT > 1) {
-    if (kg > 0) red[(kg - 1) * 256 + rt * 64 + lane] = acc;
-    __syncthreads();
-    if (kg > 0) return;
-#pragma unroll
-    for (int h = 1; h < KSPLIT; ++h) acc += red[(h - 1) * 256 + rt * 64 + lane];
-  }
-  if (!smp_ok) return;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t orow = (int64_t)tl.row0 + rt * 16 + 4 * q + r;
-    if (orow >= rows) continue;
-    if (nd.root)
-      est[(int64_t)nd.net * S + sample0 + smp] = (double)acc[r];
-    else
-      wbuf[smp * w_row + nd.w_off + orow] = (A)acc[r];
-  }
-}
 
 // Export hook: x_k = C_{parent,k} w_k for non-root tensors (w_k = X_k for leaves).
 template <typename T, typename A>
@@ -846,9 +754,12 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
   const size_t lds = (size_t)p->m * 8 + (size_t)P->tcap * 12;
   auto gk = m2_gather_kernel<T, A>;
   constexpr size_t g16 = g16_lds_bytes<T, A>();
-  if (g16 > 65536)
-    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A>,
+  if (g16 > 65536) {
+    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, false>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
+    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, true>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
+  }
   if (lds > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)gk, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
@@ -870,23 +781,8 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     const A *gb = reinterpret_cast<const A *>(P->d_g);
     A *wb = reinterpret_cast<A *>(P->d_w);
     const M2Tile *tl = P->d_level_tiles[(size_t)d];
-    if (p->flags & TN_FLAG_MFMA_BF16) {
-      // Column split: enough waves for four per SIMD (256 CUs x 4), each group
-      // of four waves still taking at least 8 chunks of 32 columns.
-      dim3 g2((unsigned)P->level_tiles[(size_t)d].size(), (unsigned)((n + kGemmSamples - 1) / kGemmSamples));
-      const int64_t waves = 4ll * g2.x * g2.y;
-      int ks = 1;
-      while (ks < 4 && waves * ks < 4096 && P->level_maxcols[(size_t)d] >= 512ll * ks) ks *= 2;
-      if (ks == 1)
-        hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 1>), g2, dim3(256), 0, st, P->d_nodes, tl, dp, gb,
-                           P->g_row, n, wb, P->w_row, est, p->S, c0);
-      else if (ks == 2)
-        hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 2>), g2, dim3(512), 0, st, P->d_nodes, tl, dp, gb,
-                           P->g_row, n, wb, P->w_row, est, p->S, c0);
-      else
-        hipLaunchKernelGGL((m2_gemm_bf16_kernel<T, A, 4>), g2, dim3(1024), 0, st, P->d_nodes, tl, dp, gb,
-                           P->g_row, n, wb, P->w_row, est, p->S, c0);
-    } else if (d == 0) {  // roots only, one row each
+    const bool bf = (p->flags & TN_FLAG_MFMA_BF16) != 0;
+    if (d == 0 && !bf) {  // roots only, one row each
       dim3 g3((unsigned)P->level_tiles[0].size(), (unsigned)((n + kRootSamples - 1) / kRootSamples));
       hipLaunchKernelGGL((m2_root_kernel<T, A>), g3, dim3(256), 0, st, P->d_nodes, tl, dp, gb, P->g_row, n, est,
                          p->S, c0);
@@ -895,8 +791,12 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
       const int32_t z = P->level_splits[(size_t)d];
       dim3 g4((unsigned)nt, (unsigned)((n + kG16Samples - 1) / kG16Samples), (unsigned)z);
       double *part = z > 1 ? P->d_part : nullptr;
-      hipLaunchKernelGGL((m2_gemm16_kernel<T, A>), g4, dim3(kG16Threads), g16, st, P->d_nodes,
-                         tl, nt, dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+      if (bf)
+        hipLaunchKernelGGL((m2_gemm16_kernel<T, A, true>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt, dp,
+                           gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+      else
+        hipLaunchKernelGGL((m2_gemm16_kernel<T, A, false>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt, dp,
+                           gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
       TN_HIP_CHECK(hipGetLastError());
       if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
       if (z > 1) {  // the partials' sum is timed with the gathers
@@ -1123,7 +1023,7 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
     level_cols[(size_t)nd.depth] += (nd.ncols + 3) & ~3ll;  // 4-aligned rows of g
     P->level_nodes[(size_t)nd.depth].push_back((int32_t)i);
     P->level_maxcols[(size_t)nd.depth] = std::max(P->level_maxcols[(size_t)nd.depth], nd.ncols);
-    for (int r0 = 0; r0 < nd.rows; r0 += kGemmRows) P->level_tiles[(size_t)nd.depth].push_back({(int32_t)i, r0});
+    for (int r0 = 0; r0 < nd.rows; r0 += kG16Rows) P->level_tiles[(size_t)nd.depth].push_back({(int32_t)i, r0});
   }
   for (int64_t v : level_cols) P->g_row = std::max(P->g_row, v);
   if (P->g_row > 65535ll * 65536ll)
