@@ -85,6 +85,10 @@ struct M2Plan {
   std::vector<int32_t> level_splits;              // per depth: column ranges of the FP64 product
   std::vector<int32_t> level_kcols;               // per depth: columns per range
   double *d_part = nullptr;                       // column-split partials (largest level)
+  uint32_t *d_ltab = nullptr;                     // slot tables: [tensor of all_nodes][sample][tcap]
+  std::vector<int32_t> all_nodes;                 // tensors with children, depth by depth
+  std::vector<int64_t> level_off;                 // per depth: its first position in all_nodes
+  int32_t *d_all_nodes = nullptr;
   std::vector<int32_t *> d_level_nodes;
   std::vector<M2Tile *> d_level_tiles;
   int64_t g_row = 0;    // entries of g per sample (max over depths)
@@ -253,70 +257,149 @@ __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab
   const double w1 = active ? wv[tab_base[1] + (int32_t)i1] : 0.0;
   const double kMagic = 6755399441055744.0;
   const long long kMagicBits = __double_as_longlong(kMagic);
+  // U rows per step, their table and w reads issued before the dependent LDS
+  // operations (the compiler cannot reorder them across the atomics itself:
+  // both arrays live in the same LDS allocation).  Rows past d0 read row d0 - 1
+  // and are dropped.
+  constexpr int U = 4;
   if (active) {
-    for (uint32_t i0 = i0s; i0 < d0; i0 += R) {
-      const uint32_t v0 = t0[i0];
-      const uint32_t b = ((v0 & 0x7fffffffu) + v1m) & mask;
-      const long long sg = (long long)((v0 ^ v1) & 0x80000000u) << 32;
-      const double p = __longlong_as_double(__double_as_longlong(w0[i0] * w1) ^ sg);
-      atomicAdd(&acc[b], (unsigned long long)(__double_as_longlong(fma(p, sc, kMagic)) - kMagicBits));
+    for (uint32_t i0 = i0s; i0 < d0; i0 += U * R) {
+      uint32_t v0[U];
+      double x0[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t ii = min(i0 + u * R, d0 - 1);
+        v0[u] = t0[ii];
+        x0[u] = w0[ii];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (i0 + u * R < d0) {
+          const uint32_t b = ((v0[u] & 0x7fffffffu) + v1m) & mask;
+          const long long sg = (long long)((v0[u] ^ v1) & 0x80000000u) << 32;
+          const double p = __longlong_as_double(__double_as_longlong(x0[u] * w1) ^ sg);
+          atomicAdd(&acc[b], (unsigned long long)(__double_as_longlong(fma(p, sc, kMagic)) - kMagicBits));
+        }
+      }
     }
   }
   __syncthreads();
   if (active) {
-    for (uint32_t i0 = i0s; i0 < d0; i0 += R) {
-      const uint32_t v0 = t0[i0];
-      const uint32_t b = ((v0 & 0x7fffffffu) + v1m) & mask;
-      const A r = (A)((double)(long long)acc[b] * inv_sc);
-      g[(size_t)i0 * d1 + i1] = ((v0 ^ v1) & 0x80000000u) ? -r : r;
+    for (uint32_t i0 = i0s; i0 < d0; i0 += U * R) {
+      uint32_t v0[U];
+      unsigned long long a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v0[u] = t0[min(i0 + u * R, d0 - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] = acc[((v0[u] & 0x7fffffffu) + v1m) & mask];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t ii = i0 + u * R;
+        if (ii < d0) {
+          const A r = (A)((double)(long long)a[u] * inv_sc);
+          g[(size_t)ii * d1 + i1] = ((v0[u] ^ v1) & 0x80000000u) ? -r : r;
+        }
+      }
     }
   }
 }
 
-// One sample's sketch r_k and gather g for tensor k (see the file comment).
+// Hash coefficients of tensor nd for one sample: child contractions [0, c),
+// tensor sketches [c, c + 2(qt-1)), padding slots after that; thread tid < c +
+// 2(qt-1) + (qt-c) writes coef[tid].
+__device__ __forceinline__ void node_coeffs(const M2Node &nd, uint64_t sample, HashCoeffs *coef) {
+  const int tid = threadIdx.x, c = nd.nchild, qt = nd.qt, n_t = 2 * (qt - 1);
+  if (tid >= c + n_t + (qt - c)) return;
+  uint64_t stream;
+  if (tid < c) {
+    stream = (uint64_t)nd.child_edge[tid];
+  } else if (tid < c + n_t) {
+    const int k = tid - c, tix = k >> 1, d = k & 1;
+    // tix enumerates (level l, index j) level-major from l = qt: tix = qt - l + j
+    int l = qt, base = 0;
+    while (tix - base >= l / 2) { base += l / 2; l /= 2; }
+    stream = (1ull << 62) + ((uint64_t)nd.local << 32) + ((uint64_t)l << 16) + (uint64_t)(2 * (tix - base) + d);
+  } else {
+    stream = (1ull << 63) + ((uint64_t)nd.local << 32) + (uint64_t)(c + tid - c - n_t);
+  }
+  coef[tid] = hash_coeffs(nd.seed, sample, stream);
+}
+
+// Level-one slot tables of every (tensor with children, sample), one wave per
+// pair: the child (or padding) count sketch of each slot, combined with the
+// first tensor sketch of its pair when qt >= 2 (Algorithm 4's first level),
+// packed as bucket | sign << 31.  out: [tensor of `list`][sample][tcap], `list`
+// holding the tensors of every depth (the gather of depth d reads from its
+// offset).  Computed apart from the gathers, in one launch per estimate, so
+// that the serial hash arithmetic of one sample does not hold up the LDS work
+// of another.
+constexpr int kTabThreads = 64;
+
+__global__ __launch_bounds__(kTabThreads) void m2_tables_kernel(const M2Node *__restrict__ nodes,
+                                                                const int32_t *__restrict__ list,
+                                                                const int32_t *__restrict__ tables, int64_t W,
+                                                                int64_t sample0, int64_t n_samples, int log2m,
+                                                                uint32_t *__restrict__ out, int tcap) {
+  __shared__ HashCoeffs coef[3 * kM2MaxChildren];
+  const M2Node &nd = nodes[list[blockIdx.x]];
+  const int64_t s = blockIdx.y;
+  const int tid = threadIdx.x, c = nd.nchild, qt = nd.qt, n_t = 2 * (qt - 1);
+  const uint32_t m = 1u << log2m, mask = m - 1;
+  const int32_t *tab = tables ? tables + s * W : nullptr;
+  if (!tab) node_coeffs(nd, (uint64_t)(sample0 + s), coef);  // at most 3 * 8 <= 64 streams
+  __syncthreads();
+  uint32_t *row = out + ((int64_t)blockIdx.x * n_samples + s) * tcap;
+  int base = 0;
+  for (int j = 0; j < qt; ++j) {
+    const int nj = j < c ? nd.child_dim[j] : 1;
+    for (int i = tid; i < nj; i += kTabThreads) {
+      uint32_t v;
+      if (j < c)
+        v = tab ? (uint32_t)tab[nd.child_tab[j] + i] : hash_packed(coef[j], (uint32_t)i, mask);
+      else
+        v = tab ? (uint32_t)tab[nd.pad_tab[j]] : hash_packed(coef[c + n_t + (j - c)], 0u, mask);
+      if (qt >= 2) {
+        const uint32_t t = tsketch(nd, tab, coef, c, m, mask, j >> 1, j & 1, v & 0x7fffffffu);
+        v = (t & 0x7fffffffu) | ((v ^ t) & 0x80000000u);
+      }
+      row[base + i] = v;
+    }
+    base += nj;
+  }
+}
+
+// Sketches r_k and gathers g of tensor k for the samples blockIdx.y + i gridDim.y
+// (see the file comment).  Per block, once: the slot-table bases and the leaf
+// children's w (data vectors, the same for every sample) with their max |w|.
+// Per sample: the slot tables (from m2_tables_kernel) and the non-leaf
+// children's w, both loaded into registers during the previous sample's columns
+// when they fit (at most kTPre table entries per thread; each non-leaf child at
+// most 256 values and at most kWPre of them); the hash coefficients only when
+// qt >= 4 (the column hash then evaluates the higher tensor-sketch levels); the
+// fixed-point scale, the scatter and the gather.
 // A: storage type of w and g (float for FP32/BF16 data, double for FP64).
+constexpr int kWPre = 4, kTPre = 2;
+
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void m2_gather_kernel(
     const M2Node *__restrict__ nodes, const int32_t *__restrict__ level, const void *const *data,
-    const int32_t *__restrict__ tables, int64_t W, int64_t sample0, int log2m,
-    const A *__restrict__ wbuf, int64_t w_row, A *__restrict__ gbuf, int64_t g_row,
-    double *__restrict__ r_out, int64_t r_stride, int tcap) {
+    const int32_t *__restrict__ tables, int64_t W, int64_t sample0, int64_t n_samples, int log2m,
+    const uint32_t *__restrict__ ltab, int64_t ltab_off, const A *__restrict__ wbuf, int64_t w_row, A *__restrict__ gbuf,
+    int64_t g_row, double *__restrict__ r_out, int64_t r_stride, int tcap) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ HashCoeffs coef[3 * kM2MaxChildren];
-  __shared__ unsigned long long wmax[kM2MaxChildren];
+  __shared__ unsigned long long wmax[kM2MaxChildren], wmax_leaf[kM2MaxChildren];
   __shared__ int32_t tab_base[kM2MaxChildren + 1];
 
   const M2Node &nd = nodes[level[blockIdx.x]];
-  const int64_t s = blockIdx.y;
-  const uint64_t sample = (uint64_t)(sample0 + s);
   const int tid = threadIdx.x;
   const uint32_t m = 1u << log2m, mask = m - 1;
   const int c = nd.nchild, qt = nd.qt;
-  const int32_t *tab = tables ? tables + s * W : nullptr;
 
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);  // [m]
   uint32_t *dtab = reinterpret_cast<uint32_t *>(acc + m);                  // [tcap] slot tables
   double *wv = reinterpret_cast<double *>(dtab + tcap);                    // [tcap] children's w
 
-  // Coefficients: child contractions [0, c), tensor sketches [c, c + 2(qt-1)),
-  // padding slots after that.
-  const int n_t = 2 * (qt - 1);
-  if (!tab && tid < c + n_t + (qt - c)) {
-    uint64_t stream;
-    if (tid < c) {
-      stream = (uint64_t)nd.child_edge[tid];
-    } else if (tid < c + n_t) {
-      const int k = tid - c, tix = k >> 1, d = k & 1;
-      // tix enumerates (level l, index j) level-major from l = qt: tix = qt - l + j
-      int l = qt, base = 0;
-      while (tix - base >= l / 2) { base += l / 2; l /= 2; }
-      stream = (1ull << 62) + ((uint64_t)nd.local << 32) + ((uint64_t)l << 16) +
-               (uint64_t)(2 * (tix - base) + d);
-    } else {
-      stream = (1ull << 63) + ((uint64_t)nd.local << 32) + (uint64_t)(c + tid - c - n_t);
-    }
-    coef[tid] = hash_coeffs(nd.seed, sample, stream);
-  }
   if (tid == 0) {
     int b = 0;
     for (int j = 0; j < qt; ++j) {
@@ -325,72 +408,128 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
     }
     tab_base[qt] = b;
   }
-  if (tid < kM2MaxChildren) wmax[tid] = 0ull;
-  for (uint32_t i = tid; i < m; i += 256) acc[i] = 0ull;
+  if (tid < kM2MaxChildren) wmax_leaf[tid] = 0ull;
   __syncthreads();
-
-  // Tensor-sketch lookup: packed value of T_{tix} side d at an m-valued index.
-  auto tsk = [&](int tix, int d, uint32_t idx) -> uint32_t {
-    return tsketch(nd, tab, coef, c, m, mask, tix, d, idx);
-  };
-
-  // Level-one slot tables: the child (or padding) count sketch, followed by the
-  // first tensor sketch of its pair when qt >= 2.
-  for (int j = 0; j < qt; ++j) {
-    const int nj = tab_base[j + 1] - tab_base[j];
-    for (int i = tid; i < nj; i += 256) {
-      uint32_t v;
-      if (j < c)
-        v = tab ? (uint32_t)tab[nd.child_tab[j] + i] : hash_packed(coef[j], (uint32_t)i, mask);
-      else
-        v = tab ? (uint32_t)tab[nd.pad_tab[j]] : hash_packed(coef[c + n_t + (j - c)], 0u, mask);
-      if (qt >= 2) {
-        const uint32_t t = tsk(j >> 1, j & 1, v & 0x7fffffffu);
-        v = (t & 0x7fffffffu) | ((v ^ t) & 0x80000000u);
-      }
-      dtab[tab_base[j] + i] = v;
-    }
-  }
-  // Children's w vectors and their max |w|.
+  // leaf children: w is the data vector itself
   for (int j = 0; j < c; ++j) {
+    if (nd.child_tensor[j] < 0) continue;
+    const void *xd = data[nd.child_tensor[j]];
     double lm = 0.0;
     for (int i = tid; i < nd.child_dim[j]; i += 256) {
-      const double x = nd.child_tensor[j] >= 0
-                           ? load_val<T>(data[nd.child_tensor[j]], i)
-                           : (double)wbuf[s * w_row + nd.child_w_off[j] + i];
+      const double x = load_val<T>(xd, i);
       wv[tab_base[j] + i] = x;
       lm = fmax(lm, fabs(x));
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lm = fmax(lm, __shfl_xor(lm, off, 64));
-    if ((tid & 63) == 0) atomicMax(&wmax[j], (unsigned long long)__double_as_longlong(lm));
+    if ((tid & 63) == 0) atomicMax(&wmax_leaf[j], (unsigned long long)__double_as_longlong(lm));
   }
-  __syncthreads();
-
-  // Fixed-point scale: every product is below prod_j max|w_j| < 2^e; ncols terms.
-  double pmax = 1.0;
-  for (int j = 0; j < c; ++j) pmax *= __longlong_as_double((long long)wmax[j]);
-  const int lgN = max(nd.ncols > 1 ? 64 - __clzll((unsigned long long)(nd.ncols - 1)) : 0, 11);
-  int e = 0;
-  if (pmax > 0.0) (void)frexp(pmax, &e);
-  const double sc = ldexp(1.0, 62 - lgN - e);
-  const double inv_sc = ldexp(1.0, -(62 - lgN - e));
-
-  A *g = gbuf + s * g_row + nd.g_off;
-  switch (qt) {
-    case 1: gather_columns<A, 1>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
-    case 2:
-      if (nd.child_dim[1] <= 256)
-        gather_pair<A>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
-      else
-        gather_columns<A, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g);
+  __syncthreads();  // wmax_leaf complete before any thread copies it
+  // non-leaf children eligible for the register prefetch
+  int pre_j[kWPre];
+  int n_pre = 0;
+  bool pre_ok = true;
+  for (int j = 0; j < c; ++j) {
+    if (nd.child_tensor[j] >= 0) continue;
+    if (n_pre == kWPre || nd.child_dim[j] > 256) {
+      pre_ok = false;
       break;
-    case 4: gather_columns<A, 4>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
-    default: gather_columns<A, 8>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+    }
+    pre_j[n_pre++] = j;
   }
-  if (r_out && nd.root) {
-    for (uint32_t b = tid; b < m; b += 256)
-      r_out[s * r_stride + (int64_t)nd.net * m + b] = (double)(long long)acc[b] * inv_sc;
+  A pre[kWPre];
+  uint32_t tpre[kTPre];
+  const int n_ent = tab_base[qt];  // slot-table entries of this tensor
+  const bool tpre_ok = n_ent <= 256 * kTPre;
+  const uint32_t *ltab_node = ltab + (ltab_off + blockIdx.x) * n_samples * tcap;
+  auto prefetch = [&](int64_t sp) {
+#pragma unroll
+    for (int q = 0; q < kWPre; ++q)
+      if (pre_ok && q < n_pre && tid < nd.child_dim[pre_j[q]])
+        pre[q] = wbuf[sp * w_row + nd.child_w_off[pre_j[q]] + tid];
+#pragma unroll
+    for (int q = 0; q < kTPre; ++q)
+      if (tpre_ok && tid + 256 * q < n_ent) tpre[q] = ltab_node[sp * tcap + tid + 256 * q];
+  };
+
+  const int64_t s_first = blockIdx.y, s_step = gridDim.y;
+  if (s_first < n_samples) prefetch(s_first);
+  // wmax holds the leaf maxima at the start of every sample (reset again at the
+  // end of each sample, when nothing reads it, so no barrier is added).
+  if (tid < kM2MaxChildren) wmax[tid] = wmax_leaf[tid];
+  __syncthreads();
+  for (int64_t s = s_first; s < n_samples; s += s_step) {
+    const int32_t *tab = tables ? tables + s * W : nullptr;
+    if (qt >= 4 && !tab) node_coeffs(nd, (uint64_t)(sample0 + s), coef);
+    for (uint32_t i = tid; i < m; i += 256) acc[i] = 0ull;
+    // Level-one slot tables.
+    if (tpre_ok) {
+#pragma unroll
+      for (int q = 0; q < kTPre; ++q)
+        if (tid + 256 * q < n_ent) dtab[tid + 256 * q] = tpre[q];
+    } else {
+      for (int i = tid; i < n_ent; i += 256) dtab[i] = ltab_node[s * tcap + i];
+    }
+    // Non-leaf children's w and their max |w|.
+    if (pre_ok) {
+#pragma unroll
+      for (int q = 0; q < kWPre; ++q) {
+        if (q >= n_pre) break;
+        const int j = pre_j[q];
+        double lm = 0.0;
+        if (tid < nd.child_dim[j]) {
+          const double x = (double)pre[q];
+          wv[tab_base[j] + tid] = x;
+          lm = fabs(x);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lm = fmax(lm, __shfl_xor(lm, off, 64));
+        if ((tid & 63) == 0) atomicMax(&wmax[j], (unsigned long long)__double_as_longlong(lm));
+      }
+    } else {
+      for (int j = 0; j < c; ++j) {
+        if (nd.child_tensor[j] >= 0) continue;
+        double lm = 0.0;
+        for (int i = tid; i < nd.child_dim[j]; i += 256) {
+          const double x = (double)wbuf[s * w_row + nd.child_w_off[j] + i];
+          wv[tab_base[j] + i] = x;
+          lm = fmax(lm, fabs(x));
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) lm = fmax(lm, __shfl_xor(lm, off, 64));
+        if ((tid & 63) == 0) atomicMax(&wmax[j], (unsigned long long)__double_as_longlong(lm));
+      }
+    }
+    __syncthreads();
+    if (s + s_step < n_samples) prefetch(s + s_step);  // in flight during the columns
+
+    // Fixed-point scale: every product is below prod_j max|w_j| < 2^e; ncols terms.
+    double pmax = 1.0;
+    for (int j = 0; j < c; ++j) pmax *= __longlong_as_double((long long)wmax[j]);
+    const int lgN = max(nd.ncols > 1 ? 64 - __clzll((unsigned long long)(nd.ncols - 1)) : 0, 11);
+    int e = 0;
+    if (pmax > 0.0) (void)frexp(pmax, &e);
+    const double sc = ldexp(1.0, 62 - lgN - e);
+    const double inv_sc = ldexp(1.0, -(62 - lgN - e));
+
+    A *g = gbuf + s * g_row + nd.g_off;
+    switch (qt) {
+      case 1: gather_columns<A, 1>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      case 2:
+        if (nd.child_dim[1] <= 256)
+          gather_pair<A>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
+        else
+          gather_columns<A, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g);
+        break;
+      case 4: gather_columns<A, 4>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      default: gather_columns<A, 8>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+    }
+    if (r_out && nd.root) {
+      for (uint32_t b = tid; b < m; b += 256)
+        r_out[s * r_stride + (int64_t)nd.net * m + b] = (double)(long long)acc[b] * inv_sc;
+    }
+    if (tid < kM2MaxChildren) wmax[tid] = wmax_leaf[tid];
+    __syncthreads();  // acc, coef, the tables and wmax are rewritten for the next sample
   }
 }
 
@@ -763,14 +902,26 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
   if (lds > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)gk, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
+  if (!P->all_nodes.empty()) {
+    hipEvent_t ev = nullptr;
+    int rc;
+    if ((rc = prof_begin(p, st, &ev, TN_KERNEL_HASH)) != TN_OK) return rc;
+    hipLaunchKernelGGL(m2_tables_kernel, dim3((unsigned)P->all_nodes.size(), (unsigned)n), dim3(kTabThreads), 0, st,
+                       P->d_nodes, P->d_all_nodes, tables, p->W, c0, n, p->log2m, P->d_ltab, P->tcap);
+    TN_HIP_CHECK(hipGetLastError());
+    if ((rc = prof_end(p, st, TN_KERNEL_HASH, ev)) != TN_OK) return rc;
+  }
   for (int d = (int)P->level_nodes.size() - 1; d >= 0; --d) {
     if (P->level_nodes[(size_t)d].empty()) continue;
     hipEvent_t ev = nullptr;
     int rc;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
-    dim3 g1((unsigned)P->level_nodes[(size_t)d].size(), (unsigned)n);
+    // Samples per block: about 1024 blocks per level (four resident per CU).
+    const int64_t nn = (int64_t)P->level_nodes[(size_t)d].size();
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, (1024 + nn - 1) / nn));
+    dim3 g1((unsigned)nn, (unsigned)gy);
     hipLaunchKernelGGL(gk, g1, dim3(256), lds, st, P->d_nodes, P->d_level_nodes[(size_t)d],
-                       (const void *const *)p->d_data, tables, p->W, c0, p->log2m,
+                       (const void *const *)p->d_data, tables, p->W, c0, n, p->log2m, P->d_ltab, P->level_off[(size_t)d],
                        reinterpret_cast<const A *>(P->d_w), P->w_row,
                        reinterpret_cast<A *>(P->d_g), P->g_row,
                        export_out ? P->d_r : nullptr, (int64_t)p->n_nets * p->m, P->tcap);
@@ -1026,10 +1177,16 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
     for (int r0 = 0; r0 < nd.rows; r0 += kG16Rows) P->level_tiles[(size_t)nd.depth].push_back({(int32_t)i, r0});
   }
   for (int64_t v : level_cols) P->g_row = std::max(P->g_row, v);
+  P->level_off.assign(P->level_nodes.size(), 0);
+  for (size_t d = 0; d < P->level_nodes.size(); ++d) {
+    P->level_off[d] = (int64_t)P->all_nodes.size();
+    P->all_nodes.insert(P->all_nodes.end(), P->level_nodes[d].begin(), P->level_nodes[d].end());
+  }
   if (P->g_row > 65535ll * 65536ll)
     return set_error(TN_ERR_UNSUPPORTED, "acyclic method: level too large");
   // sample chunk: g and w rows within a 2 GiB workspace, at most 65535 samples
-  const size_t per_sample = (size_t)(P->g_row + P->w_row) * as + (size_t)p->n_nets * p->m * 8;
+  const size_t per_sample = (size_t)(P->g_row + P->w_row) * as + (size_t)p->n_nets * p->m * 8 +
+                            P->all_nodes.size() * (size_t)P->tcap * 4;
   int64_t chunk = (int64_t)std::max<size_t>(1, ((size_t)2 << 30) / std::max<size_t>(1, per_sample));
   chunk = std::min<int64_t>({chunk, p->S, 65535});
   P->chunk = chunk;
@@ -1083,6 +1240,10 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   void *q = nullptr;
   if ((rc = alloc(&q, part * 8)) != TN_OK) return rc;
   P->d_part = reinterpret_cast<double *>(q);
+  void *lt = nullptr;
+  if ((rc = alloc(&lt, P->all_nodes.size() * (size_t)chunk * (size_t)P->tcap * 4)) != TN_OK) return rc;
+  P->d_ltab = reinterpret_cast<uint32_t *>(lt);
+  if ((rc = upload_vec(&P->d_all_nodes, P->all_nodes)) != TN_OK) return rc;
   return TN_OK;
 }
 
@@ -1125,6 +1286,8 @@ void m2_release(tn_plan *p) {
   if (P->d_w) (void)hipFree(P->d_w);
   if (P->d_r) (void)hipFree(P->d_r);
   if (P->d_part) (void)hipFree(P->d_part);
+  if (P->d_ltab) (void)hipFree(P->d_ltab);
+  if (P->d_all_nodes) (void)hipFree(P->d_all_nodes);
   delete P;
   p->m2 = nullptr;
 }
