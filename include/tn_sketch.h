@@ -126,7 +126,12 @@ typedef struct tn_plan tn_plan;
  *                  here, it is bound by each tn_sketch_estimate call).
  *   method       : TN_CYCLIC (any network) or TN_ACYCLIC (trees only).
  *   m            : sketch size (the paper's m), a power of two,
- *                  1 <= m <= 16384 for TN_CYCLIC (8192 with TN_F64 data),
+ *                  1 <= m <= 65536 for TN_CYCLIC (above 16384 the scatter
+ *                  splits each sketch's buckets over blocks and takes one
+ *                  sample per pass; when the m-point FFT does not fit in LDS,
+ *                  from 16384 with TN_F64 data and 32768 otherwise, the combine
+ *                  runs in two passes through a device workspace of
+ *                  tensors x m complex values per sample),
  *                  2 <= m <= 8192 for TN_ACYCLIC.
  *   samples      : S >= 1 independent sketch samples per network; sample r
  *                  uses hash key (seed + j, r, stream) for network j.

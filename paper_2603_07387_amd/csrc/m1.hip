@@ -32,11 +32,13 @@ using namespace m1dev;
 // scatter_slot), then writes them out as floating point.
 // Blocks of 256 threads with one bank, 512 with two (twice the accumulator LDS
 // per block, the same waves per CU).
-template <typename T, typename A, int SB, int BANKS>
+// RANGED (m above kMaxLog2Acc buckets): blockIdx.z selects the range of
+// 2^log2acc buckets the block accumulates (one bank, one sample per pass).
+template <typename T, typename A, int SB, int BANKS, bool RANGED = false>
 __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
-    int64_t samples, int log2m, int64_t n_slots, A *__restrict__ ybuf) {
+    int64_t samples, int log2m, int log2acc, int64_t n_slots, A *__restrict__ ybuf) {
   // No static LDS: the accumulators start at LDS address 0, so their offsets
   // need no base add per term.
   extern __shared__ __align__(16) unsigned char smem[];
@@ -44,10 +46,12 @@ __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
   const int tid = threadIdx.x;
   const int64_t s0 = (int64_t)blockIdx.y * SB;
   const int nsb = (int)min((int64_t)SB, samples - s0);
-  const uint32_t m = 1u << log2m, mask = m - 1;
+  const uint32_t m = 1u << log2m;
+  const uint32_t ma = RANGED ? 1u << log2acc : m, amask = ma - 1;  // accumulator words per sample
+  const uint32_t r0 = RANGED ? blockIdx.z * ma : 0u;              // first bucket of the range
   // BANKS banks of m words per sample (see scatter_slot), then the tables
   const uint32_t signbit = BANKS == 2 ? sign_bank_offset(SB, m) : 0u;
-  const size_t acc_bytes = BANKS == 2 ? sign_bank_bytes(SB, m) : (size_t)SB * 8 * m;
+  const size_t acc_bytes = BANKS == 2 ? sign_bank_bytes(SB, m) : (size_t)SB * 8 * ma;
   const size_t acc_end = (acc_bytes + 15) & ~(size_t)15;
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
   unsigned long long *s_max = reinterpret_cast<unsigned long long *>(smem + acc_end);  // [2]
@@ -59,15 +63,16 @@ __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
   const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
   FixedScale fs;
   fs.lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
-  scatter_slot<T, SB, BANKS, NT>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * m, signbit, colt,
-                             rowt, s_max, fs);
+  scatter_slot<T, SB, BANKS, NT, RANGED>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * ma, signbit,
+                                         colt, rowt, s_max, fs, blockIdx.z, RANGED ? log2acc : -1);
   const unsigned long long *neg = acc + signbit / 8;
-  for (int i = tid; i < nsb * (int)m; i += NT) {
-    const int s = i >> log2m;
-    const int b = i & mask;
+  const int lga = RANGED ? log2acc : log2m;
+  for (int i = tid; i < (nsb << lga); i += NT) {
+    const int s = i >> lga;
+    const int b = i & (int)amask;
     // positive bank minus negative bank
     const long long v = BANKS == 2 ? (long long)(acc[i] - neg[i]) : (long long)acc[i];
-    ybuf[((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + b] = (A)ldexp((double)v, -fs.scale);
+    ybuf[((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + r0 + b] = (A)ldexp((double)v, -fs.scale);
   }
 }
 
@@ -140,6 +145,112 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
   if (tid == 0) est[(int64_t)blockIdx.x * S + sample0 + s] = tot / (double)M;
 }
 
+// ---------------------------------------------------------------------------
+// Combine when the m-point FFT does not fit in LDS (m = 2^14 with FP64 data,
+// m >= 2^15):
+// the same estimate (1/m) Re sum_j prod_k Y_k[j], with each Y_k = F y_k taken in
+// two passes through HBM.  With m = n1 n2 (n2 = 256), b = b1 + n1 b2 and
+// j = j2 + n2 j1,
+//   Y[j2 + n2 j1] = sum_b1 w_n1^(b1 j1) w_m^(b1 j2) sum_b2 y[b1 + n1 b2] w_n2^(b2 j2),
+// w_n = exp(-2 pi i / n).  Pass 1 (per tensor and sample): the n2-point DFTs
+// over b2 of each column b1, times w_m^(b1 j2), stored transposed as
+// C[j2][b1].  Pass 2 (per network and sample, rows j2 split over blocks): the
+// n1-point DFT of each row of every tensor gives Y at the n1 frequencies
+// j2 + n2 j1; their product over the network's tensors, in FP64, is summed
+// over the row.  Every frequency is visited once, so the order of the sum is
+// fixed and the result matches the in-LDS combine up to FFT rounding.
+constexpr int kBigN2 = 256, kBigCols = 8, kBigRows = 4;
+
+// w_m^e from the half table tw[j] = w_m^j, j < m/2.
+template <typename A2>
+__device__ __forceinline__ A2 twiddle_at(const A2 *__restrict__ tw, uint32_t e, uint32_t m) {
+  e &= m - 1;
+  if (e < m / 2) return tw[e];
+  const A2 t = tw[e - m / 2];
+  return A2{-t.x, -t.y};
+}
+
+template <typename A>
+__global__ __launch_bounds__(256) void m1_big_cols_kernel(const int32_t *__restrict__ tslot,
+                                                          const A *__restrict__ ybuf, int64_t n_slots,
+                                                          int64_t n_tensors, int log2m,
+                                                          const typename Cplx<A>::type *__restrict__ tw,
+                                                          typename Cplx<A>::type *__restrict__ cbuf) {
+  using A2 = typename Cplx<A>::type;
+  __shared__ A2 z[kBigCols][kBigN2];
+  __shared__ A2 tw2[kBigN2 / 2];
+  const uint32_t m = 1u << log2m, n1 = m / kBigN2;
+  const int64_t k = blockIdx.x, s = blockIdx.y;
+  const uint32_t b1_0 = blockIdx.z * kBigCols;
+  const int tid = threadIdx.x;
+  if (tid < kBigN2 / 2) tw2[tid] = tw[(uint32_t)tid * n1];  // w_n2^t = w_m^(t n1)
+  const A *y = ybuf + s * n_slots * (int64_t)m;
+  // column b1 = b1_0 + c: y[b1 + n1 b2], b2 = tid, summed over the tensor's slots
+#pragma unroll 4
+  for (int c = 0; c < kBigCols; ++c) {
+    A v = 0;
+    for (int sl = tslot[k]; sl < tslot[k + 1]; ++sl) v += y[(int64_t)sl * m + b1_0 + c + (int64_t)n1 * tid];
+    z[c][bitrev<8>(tid)] = A2{v, (A)0};
+  }
+  __syncthreads();
+  for (int c = 0; c < kBigCols; ++c) fft_lds<A, 8>(z[c], tw2);  // ends with a barrier
+  // C[j2][b1] = Z_b1[j2] w_m^(b1 j2); thread j2 writes kBigCols consecutive b1
+  A2 *out = cbuf + (s * n_tensors + k) * (int64_t)m + (int64_t)tid * n1 + b1_0;
+#pragma unroll 4
+  for (int c = 0; c < kBigCols; ++c) {
+    const A2 v = z[c][tid], w = twiddle_at(tw, (b1_0 + c) * (uint32_t)tid, m);
+    out[c] = A2{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+  }
+}
+
+template <typename A, int LOG2N1>
+__global__ __launch_bounds__(256) void m1_big_rows_kernel(const NetDesc *__restrict__ nets,
+                                                          const typename Cplx<A>::type *__restrict__ cbuf,
+                                                          int64_t n_tensors, const typename Cplx<A>::type *__restrict__ tw,
+                                                          double *__restrict__ partial) {
+  using A2 = typename Cplx<A>::type;
+  constexpr int N1 = 1 << LOG2N1;
+  constexpr uint32_t M = (uint32_t)N1 * kBigN2;
+  __shared__ A2 z[N1];
+  __shared__ A2 tw1[N1 / 2];
+  __shared__ double red[4];
+  const NetDesc nd = nets[blockIdx.x];
+  const int64_t s = blockIdx.y;
+  const int tid = threadIdx.x;
+  if (tid < N1 / 2) tw1[tid] = tw[(uint32_t)tid * kBigN2];  // w_n1^t = w_m^(t n2)
+  double acc = 0.0;
+  for (int r = 0; r < kBigRows; ++r) {
+    const uint32_t j2 = blockIdx.z * kBigRows + r;
+    double pr = 1.0, pi = 0.0;
+    for (int k = nd.t0; k < nd.t1; ++k) {
+      __syncthreads();  // the previous transform's readers are done (and tw1 is written)
+      if (tid < N1) z[bitrev<LOG2N1>(tid)] = cbuf[(s * n_tensors + k) * (int64_t)M + (int64_t)j2 * N1 + tid];
+      __syncthreads();
+      fft_lds<A, LOG2N1>(z, tw1);
+      if (tid < N1) {
+        const double yr = z[tid].x, yi = z[tid].y;
+        const double nr = pr * yr - pi * yi;
+        pi = pr * yi + pi * yr;
+        pr = nr;
+      }
+    }
+    if (tid < N1) acc += pr;
+  }
+  const double tot = block_sum_256(acc, red);
+  if (tid == 0) partial[((int64_t)blockIdx.x * gridDim.y + s) * gridDim.z + blockIdx.z] = tot;
+}
+
+__global__ __launch_bounds__(256) void m1_big_sum_kernel(const double *__restrict__ partial, int64_t n_nets,
+                                                         int64_t samples, int parts, int64_t sample0, int64_t S,
+                                                         double inv_m, double *__restrict__ est) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // (network, sample)
+  if (i >= n_nets * samples) return;
+  const int64_t net = i / samples, s = i - net * samples;
+  double v = 0.0;
+  for (int q = 0; q < parts; ++q) v += partial[i * parts + q];
+  est[net * S + sample0 + s] = v * inv_m;
+}
+
 __global__ __launch_bounds__(256) void sample_stats_kernel(const double *__restrict__ est,
                                                            int64_t S, double *__restrict__ stats) {
   __shared__ double red[4];
@@ -188,13 +299,18 @@ __global__ void twiddle_kernel(int64_t m, typename Cplx<A>::type *out) {
 
 template <typename T, typename A, int SB>
 int scatter_sb(const M1Launch &L, hipStream_t st) {
-  auto kern = L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2> : m1_scatter_kernel<T, A, SB, 1>;
+  const bool ranged = L.log2m > kMaxLog2Acc;
+  if (ranged && (SB != 1 || L.banks != 1))
+    return set_error(TN_ERR_ARG, "scatter: m = 2^%d takes one bank and one sample per pass", L.log2m);
+  auto kern = ranged ? m1_scatter_kernel<T, A, SB, 1, true>
+                     : (L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2> : m1_scatter_kernel<T, A, SB, 1>);
   if (L.lds_bytes > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)L.lds_bytes));
-  dim3 grid((unsigned)L.n_slots, (unsigned)((L.samples + SB - 1) / SB));
+  dim3 grid((unsigned)L.n_slots, (unsigned)((L.samples + SB - 1) / SB),
+            ranged ? 1u << (L.log2m - kMaxLog2Acc) : 1u);
   hipLaunchKernelGGL(kern, grid, dim3(256 * L.banks), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
-                     L.W, L.samples, L.log2m, L.n_slots, reinterpret_cast<A *>(L.ybuf));
+                     L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, reinterpret_cast<A *>(L.ybuf));
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }
@@ -225,6 +341,34 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const v
   hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, nets, tslot,
                      reinterpret_cast<const A *>(ybuf), n_slots, sample0, S,
                      reinterpret_cast<const A2 *>(tw), est);
+  TN_HIP_CHECK(hipGetLastError());
+  return TN_OK;
+}
+
+template <typename A>
+int combine_big(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const void *ybuf,
+                int64_t n_slots, int64_t n_tensors, int64_t samples, int64_t sample0, int64_t S, int log2m,
+                const void *tw, void *cbuf, double *partial, double *est, hipStream_t st) {
+  using A2 = typename Cplx<A>::type;
+  const uint32_t m = 1u << log2m, n1 = m / kBigN2;
+  hipLaunchKernelGGL(m1_big_cols_kernel<A>, dim3((unsigned)n_tensors, (unsigned)samples, n1 / kBigCols), dim3(256), 0,
+                     st, tslot, reinterpret_cast<const A *>(ybuf), n_slots, n_tensors, log2m,
+                     reinterpret_cast<const A2 *>(tw), reinterpret_cast<A2 *>(cbuf));
+  TN_HIP_CHECK(hipGetLastError());
+  dim3 g2((unsigned)n_nets, (unsigned)samples, kBigN2 / kBigRows);
+  if (log2m == 14)
+    hipLaunchKernelGGL((m1_big_rows_kernel<A, 6>), g2, dim3(256), 0, st, nets, reinterpret_cast<const A2 *>(cbuf),
+                       n_tensors, reinterpret_cast<const A2 *>(tw), partial);
+  else if (log2m == 15)
+    hipLaunchKernelGGL((m1_big_rows_kernel<A, 7>), g2, dim3(256), 0, st, nets, reinterpret_cast<const A2 *>(cbuf),
+                       n_tensors, reinterpret_cast<const A2 *>(tw), partial);
+  else
+    hipLaunchKernelGGL((m1_big_rows_kernel<A, 8>), g2, dim3(256), 0, st, nets, reinterpret_cast<const A2 *>(cbuf),
+                       n_tensors, reinterpret_cast<const A2 *>(tw), partial);
+  TN_HIP_CHECK(hipGetLastError());
+  const int64_t pairs = n_nets * samples;
+  hipLaunchKernelGGL(m1_big_sum_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, partial, n_nets,
+                     samples, kBigN2 / kBigRows, sample0, S, 1.0 / (double)m, est);
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }
@@ -269,6 +413,21 @@ int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tslot,
                              est, st);
   return combine_t<float>(nets, n_nets, tslot, ybuf, n_slots, samples, sample0, S, log2m, tw, est,
                           st);
+}
+
+int launch_m1_combine_big(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, int dtype,
+                          const void *ybuf, int64_t n_slots, int64_t n_tensors, int64_t samples,
+                          int64_t sample0, int64_t S, int log2m, const void *tw, void *cbuf, double *partial,
+                          double *est, hipStream_t st) {
+  if (n_nets == 0 || samples == 0) return TN_OK;
+  if (samples > 65535) return set_error(TN_ERR_UNSUPPORTED, "combine: samples per launch");
+  if (log2m < kMaxLog2Acc || log2m > kMaxLog2M1)
+    return set_error(TN_ERR_ARG, "two-pass combine: m = 2^%d", log2m);
+  if (dtype == TN_F64)
+    return combine_big<double>(nets, n_nets, tslot, ybuf, n_slots, n_tensors, samples, sample0, S, log2m, tw,
+                               cbuf, partial, est, st);
+  return combine_big<float>(nets, n_nets, tslot, ybuf, n_slots, n_tensors, samples, sample0, S, log2m, tw, cbuf,
+                            partial, est, st);
 }
 
 int launch_m1_slots_to_tensors(const int32_t *tslot, int64_t n_tensors, int dtype,

@@ -122,13 +122,21 @@ __host__ __device__ constexpr size_t sign_bank_bytes(int sb, uint32_t m) {
 // loads.  s_max (2 words of LDS) holds the running maximum; both it and fs
 // carry over between calls that feed the same sketches.  All NT threads of
 // the block call it; it starts and ends with a barrier.
-template <typename T, int SB, int BANKS, int NT>
+// RANGED (one bank): the LDS holds only the 2^log2acc buckets starting at
+// bucket rsel * 2^log2acc of each sketch; terms outside that range are
+// dropped.  Every range sees the same terms in the same order, so all ranges
+// of a slot reach the same fixed-point scale.
+template <typename T, int SB, int BANKS, int NT, bool RANGED = false>
 __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDesc *__restrict__ modes,
                                              const void *const *__restrict__ data,
                                              const int32_t *__restrict__ tables, int64_t W, int nsb,
                                              int log2m, unsigned long long *acc, uint32_t sbytes,
                                              uint32_t signbit, uint32_t *colt, uint32_t *rowt,
-                                             unsigned long long *s_max, FixedScale &fs) {
+                                             unsigned long long *s_max, FixedScale &fs, uint32_t rsel = 0,
+                                             int log2acc = -1) {
+  static_assert(!RANGED || BANKS == 1, "bucket ranges use one bank");
+  if (log2acc < 0) log2acc = log2m;
+  const uint32_t rshift = 3u + (uint32_t)log2acc;  // byte offset >> rshift = range index
   const int tid = threadIdx.x;
   const uint32_t m = 1u << log2m, mask = m - 1;
   const int L = sl.L, rows = sl.rows;
@@ -171,9 +179,9 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       const int ns = 62 - fs.lgN - e;
       if (fs.bound > 0.0 && fs.scale > ns) {
         const int d = fs.scale - ns;
-        for (int i = tid; i < BANKS * nsb * (int)m; i += NT) {
-          const int si = BANKS == 2 ? i >> (log2m + 1) : i >> log2m;
-          const int bank = BANKS == 2 ? (i >> log2m) & 1 : 0, b = i & (int)mask;
+        for (int i = tid; i < (BANKS * nsb) << log2acc; i += NT) {
+          const int si = BANKS == 2 ? i >> (log2acc + 1) : i >> log2acc;
+          const int bank = BANKS == 2 ? (i >> log2acc) & 1 : 0, b = i & ((1 << log2acc) - 1);
           unsigned long long *w = reinterpret_cast<unsigned long long *>(
               reinterpret_cast<char *>(acc) + (size_t)si * sbytes + (bank ? signbit : 0u)) + b;
           *w = (unsigned long long)((long long)*w >> d);
@@ -194,6 +202,13 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
   // One fixed-point add into sample s's sketch (its sign selects the bank).
   // (nv = -v, formed once per entry for all samples of the batch.)
   auto add_fixed = [&](int s, uint32_t hv, uint32_t lv, long long v, long long nv) {
+    if constexpr (RANGED) {
+      const uint32_t o = (hv + lv) & amask;
+      if ((o >> rshift) != rsel) return;
+      atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + (o & ((1u << rshift) - 1u)) + (uint32_t)s * sbytes),
+                (unsigned long long)(((hv ^ lv) & kSignBit) ? nv : v));
+      return;
+    }
     const uint32_t a = ((hv + lv) & amask) + (uint32_t)s * sbytes;
     if constexpr (BANKS == 2)
       atomicAdd(reinterpret_cast<unsigned long long *>(acc8 + a), (unsigned long long)v);

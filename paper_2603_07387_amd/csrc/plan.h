@@ -70,6 +70,9 @@ struct tn_plan {
   tn::NetDesc *d_nets = nullptr;
   void *d_tw = nullptr;
   void *d_ybuf = nullptr;
+  bool two_pass = false;        // the m-point FFT does not fit in LDS: two-pass combine
+  void *d_cbuf = nullptr;       // the two-pass combine's transposed columns
+  double *d_partial = nullptr;  // and its per-block row sums
   int sb = 1;
   int banks = 1;            // scatter accumulator banks (autotuned: 1 or 2)
   size_t scatter_lds = 0;

@@ -48,7 +48,8 @@ size_t acc_size(int dtype) { return dtype == TN_F64 ? sizeof(double) : sizeof(fl
 // block is padded to 16 bytes and the kernel keeps a 16-byte running maximum
 // in static LDS.)
 size_t scatter_lds_for(const tn_plan *p, int sb) {
-  const size_t acc = p->banks == 2 ? m1dev::sign_bank_bytes(sb, (uint32_t)p->m) : (size_t)sb * 8 * p->m;
+  const int64_t ma = std::min<int64_t>(p->m, (int64_t)1 << kMaxLog2Acc);  // bucket ranges above
+  const size_t acc = p->banks == 2 ? m1dev::sign_bank_bytes(sb, (uint32_t)p->m) : (size_t)sb * 8 * ma;
   return acc + (size_t)sb * 4 * p->worst_cols_rows + 64;
 }
 
@@ -91,7 +92,10 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   if (p->log2m > kMaxLog2M1)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: m = %lld exceeds %d", (long long)p->m,
                      1 << kMaxLog2M1);
-  if ((size_t)p->m * 2 * as > p->max_lds)
+  const bool big = p->log2m > kMaxLog2Acc;  // bucket ranges in the scatter
+  // The combine's m-point FFT in LDS, else in two passes through HBM (m >= 2^14).
+  p->two_pass = (size_t)p->m * 2 * as > p->max_lds;
+  if (p->two_pass && p->log2m < kMaxLog2Acc)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: the m-point FFT needs %zu bytes of LDS",
                      (size_t)p->m * 2 * as);
   int64_t gmode = 0, gtensor = 0;
@@ -172,7 +176,8 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   }
   // Overrides of the untuned schedule (tests and tuning experiments; the
   // autotuner, when requested, still decides).
-  if (const char *env = getenv("TN_SCATTER_BANKS")) {
+  if (big) p->sb = 1;  // bucket ranges: one bank, one sample per pass
+  if (const char *env = getenv("TN_SCATTER_BANKS"); env && !big) {
     const int banks = atoi(env);
     if (banks == 1 || banks == 2) {
       const int save = p->banks;
@@ -181,7 +186,7 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
       else if (lds_for(p->sb) > 81920) p->sb = 1;
     }
   }
-  if (const char *env = getenv("TN_SCATTER_SB")) {
+  if (const char *env = getenv("TN_SCATTER_SB"); env && !big) {
     const int sb = atoi(env);
     if ((sb == 1 || sb == 2 || sb == 4 || sb == 8 || sb == 16) && lds_for(sb) <= p->max_lds) p->sb = sb;
   }
@@ -190,7 +195,8 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   if (p->scatter_lds > p->max_lds)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: scatter needs %zu bytes of LDS", p->scatter_lds);
 
-  const size_t per_sample = (size_t)p->W * 4 + p->h_slots.size() * (size_t)p->m * as;
+  const size_t per_sample = (size_t)p->W * 4 + p->h_slots.size() * (size_t)p->m * as +
+                            (p->two_pass ? (size_t)p->n_tensors * (size_t)p->m * 2 * as + (size_t)p->n_nets * 64 * 8 : 0);
   int64_t chunk = (int64_t)std::max<size_t>(1, kWorkspaceBudget / std::max<size_t>(1, per_sample));
   chunk = std::min<int64_t>(chunk, p->S);
   chunk = std::min<int64_t>(chunk, 65535);
@@ -244,6 +250,12 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   unsigned char *yb = nullptr;
   if ((rc = dev_alloc(&yb, (size_t)chunk * p->h_slots.size() * (size_t)p->m * as)) != TN_OK) return rc;
   p->d_ybuf = yb;
+  if (p->two_pass) {
+    unsigned char *cb = nullptr;
+    if ((rc = dev_alloc(&cb, (size_t)chunk * (size_t)p->n_tensors * (size_t)p->m * 2 * as)) != TN_OK) return rc;
+    p->d_cbuf = cb;
+    if ((rc = dev_alloc(&p->d_partial, (size_t)chunk * (size_t)p->n_nets * 64)) != TN_OK) return rc;
+  }
   if (p->m >= 2) {
     unsigned char *tw = nullptr;
     if ((rc = dev_alloc(&tw, (size_t)(p->m / 2) * 2 * as)) != TN_OK) return rc;
@@ -333,10 +345,13 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
     if ((rc = launch_m1_scatter(L, st)) != TN_OK) return rc;
     if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
-    if ((rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf,
-                                (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, est,
-                                st)) != TN_OK)
-      return rc;
+    if (p->two_pass)
+      rc = launch_m1_combine_big(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf, (int64_t)p->h_slots.size(),
+                                 p->n_tensors, n, c0, p->S, p->log2m, p->d_tw, p->d_cbuf, p->d_partial, est, st);
+    else
+      rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf, (int64_t)p->h_slots.size(), n,
+                             c0, p->S, p->log2m, p->d_tw, est, st);
+    if (rc != TN_OK) return rc;
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
   }
   return TN_OK;
@@ -360,6 +375,7 @@ struct TuneKey {
 static std::vector<std::pair<TuneKey, std::pair<int, int>>> g_tuned;
 
 int m1_autotune(tn_plan *p, hipStream_t st) {
+  if (p->log2m > kMaxLog2Acc) return TN_OK;  // bucket ranges: one schedule only
   int64_t entries = 0;
   for (const ScatterSlot &sl : p->h_slots) entries += (int64_t)sl.rows * sl.L;
   const TuneKey key{(int64_t)p->h_slots.size(), entries, p->m, p->S, p->W, p->dtype, p->fused};
@@ -666,7 +682,7 @@ void plan_release(tn_plan *p) {
   if (p->m2) m2_release(p);
   void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data,    p->d_modes,
                   p->d_slots,   p->d_tslot,  p->d_nets,     p->d_tw,      p->d_ybuf,
-                  p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn};
+                  p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn, p->d_cbuf, p->d_partial};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p->d_streams = nullptr;
@@ -676,7 +692,8 @@ void plan_release(tn_plan *p) {
   p->d_slots = nullptr;
   p->d_tslot = nullptr;
   p->d_nets = nullptr;
-  p->d_tw = p->d_ybuf = nullptr;
+  p->d_tw = p->d_ybuf = p->d_cbuf = nullptr;
+  p->d_partial = nullptr;
   p->d_est = nullptr;
   p->d_items = nullptr;
   p->d_counter = p->d_tensor_lgn = nullptr;

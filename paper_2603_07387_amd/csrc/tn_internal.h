@@ -74,7 +74,9 @@ struct NetDesc {
 // Limits of the cyclic scatter.
 constexpr int kMaxCols = 1024;          // columns per slot (packed tables in LDS)
 constexpr int kMaxSlotEntries = 1 << 16;  // entries per scatter block
-constexpr int kMaxLog2M1 = 14;          // m <= 16384 (complex FFT in LDS)
+constexpr int kMaxLog2M1 = 16;          // m <= 65536
+constexpr int kMaxLog2Acc = 14;         // sketch words in LDS per scatter block and FFT points in LDS;
+                                        // larger m: bucket ranges and the two-pass FFT
 
 struct M1Launch {
   const ScatterSlot *slots;
@@ -137,6 +139,12 @@ int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tensor
                       int dtype, const void *ybuf, int64_t n_slots, int64_t samples,
                       int64_t sample0, int64_t S, int log2m, const void *twiddles,
                       double *est, hipStream_t st);
+// m above 2^kMaxLog2Acc: the two-pass combine.  cbuf: samples x n_tensors x m
+// complex (A); partial: n_nets x samples x 64 doubles.
+int launch_m1_combine_big(const NetDesc *nets, int64_t n_nets, const int32_t *tensor_slot_begin, int dtype,
+                          const void *ybuf, int64_t n_slots, int64_t n_tensors, int64_t samples,
+                          int64_t sample0, int64_t S, int log2m, const void *tw, void *cbuf, double *partial,
+                          double *est, hipStream_t st);
 
 int launch_m1_slots_to_tensors(const int32_t *tensor_slot_begin, int64_t n_tensors, int dtype,
                                const void *ybuf, int64_t n_slots, int64_t samples, int log2m,

@@ -135,6 +135,61 @@ def test_torus_full_size(T, orc, m):
     check_estimates(orc, plan, views, 5, "float32")
 
 
+@pytest.mark.parametrize("m", [16384, 32768, 65536])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_torus_large_m(T, orc, m, dtype):
+    """m above the in-LDS FFT (two-pass combine: m = 16384 with FP64 data, all
+    of 32768 and 65536) and above the in-LDS sketch (bucket-range scatter:
+    32768 and 65536), the 4 x 4 torus (bond 16), sampled seeds."""
+    plan, views = make_plan(T, [W.torus()], dtype, m, 2, 5)
+    if m > 16384:
+        assert plan.query(8) == 1 and plan.query(10) == 1  # one sample per pass, one bank
+    check_estimates(orc, plan, views, 5, dtype)
+
+
+def test_large_m_multi_slot_and_sketches(T, orc):
+    """m = 65536 with a tensor split into several slots, a triangle and a ring in
+    one plan; the exported sketches match the oracle's bucket by bucket.  (The
+    oracle's DFT combine: its direct convolution is O(p m^2) at this m.)"""
+    big = W.Network([3, 3], [50, 40, 60, 60, 40, 50], [(0, 5), (1, 4), (2, 3)],
+                    [np.random.default_rng(5).standard_normal((50, 40, 60)),
+                     np.random.default_rng(6).standard_normal((60, 40, 50))])
+    nets = [big, W.triangle(16, seed=3), W.ring(5, 12, seed=4)]
+    m = 65536
+    plan, views = make_plan(T, nets, "float64", m, 3, 21)
+    check_estimates(orc, plan, views, 21, "float64")
+    got = plan.sketches(first=1, count=1).cpu().numpy()
+    k0 = 0
+    for j, net in enumerate(views):
+        ref = orc.m1_estimate(net, m, 21 + j, 1, combine="dft", want_sketches=True)["sketches"]
+        # A_b: the same buckets with |X| and all signs +1 (as in test_sketch_vectors)
+        tables = []
+        for e in range(net.t):
+            h, _ = orc.hash_table(21 + j, 1, e, net.dims[net.edges[e][0]], m)
+            tables.append(np.concatenate([h, np.ones_like(h)]))
+        absnet = net.with_data([np.abs(x) for x in net.data])
+        A = orc.m1_estimate(absnet, m, 0, 0, tables=tables, combine="dft", want_sketches=True)["sketches"]
+        # terms per bucket, and the 64-bit fixed point's rounding of each term:
+        # half a quantum 2^(e + lgN - 62), max|X_k| < 2^e, lgN = max(ceil log2 N, 11)
+        # for the N entries of the scatter block (at most the tensor's size)
+        ones = net.with_data([np.ones_like(x) for x in net.data])
+        cnt = orc.m1_estimate(ones, m, 0, 0, tables=tables, combine="dft", want_sketches=True)["sketches"]
+        q = np.array([2.0 ** (np.frexp(np.abs(x).max())[1] + max(int(np.ceil(np.log2(x.size))), 11) - 62)
+                      for x in net.data])
+        bar = TAU["float64"] * A + cnt * (q[:, None] / 2)
+        assert np.all(np.abs(got[0, k0:k0 + net.p] - ref) <= bar + 1e-300), j
+        k0 += net.p
+
+
+def test_m_above_65536_rejected(T):
+    import torch
+    net = W.triangle(8, seed=1)
+    spec = T.NetworkSpec.from_network(net, [torch.from_numpy(x).cuda() for x in net.data])
+    with pytest.raises(T.TNError) as e:
+        T.Plan([spec], T.TN_CYCLIC, 131072, 2, 1)
+    assert e.value.code == T.TN_ERR_UNSUPPORTED
+
+
 def test_batched_random_networks(T, orc):
     """Uneven random cyclic networks (3-12 tensors, bonds 2-32) in one plan."""
     nets = W.random_batch(count=12, seed=4)
