@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
   }
 }
 
-template <typename A, int LOG2M>
+template <typename A, int LOG2M, bool TWL>
 __global__ __launch_bounds__(256) void m1_combine_kernel(
     const NetDesc *__restrict__ nets, const int32_t *__restrict__ tslot,
     const A *__restrict__ ybuf, int64_t n_slots, int64_t sample0, int64_t S,
@@ -93,6 +93,15 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
   const int64_t s = blockIdx.y;
   const A *y = ybuf + s * n_slots * (int64_t)M;
   const int tid = threadIdx.x;
+  // Twiddles: staged in LDS after z when the launch provides the room (every
+  // butterfly pass reads them; from the global table each pass would wait on
+  // a cache round trip).
+  const A2 *twl = tw;
+  if constexpr (TWL) {
+    A2 *t = z + M;
+    for (int j = tid; j < M / 2; j += 256) t[j] = tw[j];
+    twl = t;  // the first barrier below publishes it
+  }
 
   double pr[NC], pi[NC];
 #pragma unroll
@@ -109,7 +118,7 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
       z[bitrev<LOG2M>(b)] = A2{v1, v2};
     }
     __syncthreads();
-    fft_lds<A, LOG2M>(z, tw);
+    fft_lds<A, LOG2M>(z, twl);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int j = tid + 256 * c;
@@ -332,8 +341,10 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const v
               int64_t n_slots, int64_t samples, int64_t sample0, int64_t S, const void *tw,
               double *est, hipStream_t st) {
   using A2 = typename Cplx<A>::type;
-  auto kern = m1_combine_kernel<A, LOG2M>;
-  const size_t lds = sizeof(A2) << LOG2M;
+  // z (m points) and, when the total stays within 64 KB, the m/2 twiddles
+  constexpr bool TWL = LOG2M >= 1 && (sizeof(A2) << LOG2M) * 3 / 2 <= 65536;
+  auto kern = m1_combine_kernel<A, LOG2M, TWL>;
+  const size_t lds = TWL ? (sizeof(A2) << LOG2M) * 3 / 2 : sizeof(A2) << LOG2M;
   if (lds > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
