@@ -69,6 +69,7 @@ struct M2Node {
   int64_t child_edge[kM2MaxChildren];    // stream id of the child contraction
   int64_t child_tab[kM2MaxChildren];     // its table offset
   int64_t pad_tab[kM2MaxChildren];       // table offset of padding slot j (j >= nchild)
+  int32_t child_tile0[kM2MaxChildren];   // non-leaf child: its first row tile within its depth
 };
 
 struct M2Tile {
@@ -85,6 +86,7 @@ struct M2Plan {
   std::vector<int32_t> level_splits;              // per depth: column ranges of the FP64 product
   std::vector<int32_t> level_kcols;               // per depth: columns per range
   double *d_part = nullptr;                       // column-split partials (largest level)
+  std::vector<char> level_fuse;                   // per depth: the parents' gathers sum its partials
   uint32_t *d_ltab = nullptr;                     // slot tables: [tensor of all_nodes][sample][tcap]
   std::vector<int32_t> all_nodes;                 // tensors with children, depth by depth
   std::vector<int64_t> level_off;                 // per depth: its first position in all_nodes
@@ -376,16 +378,21 @@ __global__ __launch_bounds__(kTabThreads) void m2_tables_kernel(const M2Node *__
 // when they fit (at most kTPre table entries per thread; each non-leaf child at
 // most 256 values and at most kWPre of them); the hash coefficients only when
 // qt >= 4 (the column hash then evaluates the higher tensor-sketch levels); the
-// fixed-point scale, the scatter and the gather.
+// fixed-point scale, the scatter and the gather.  With csplits > 0 the
+// non-leaf child's w is the fixed-order sum of its product's csplits column
+// partials (cpart: [split][tile of the child depth][sample][64], ctiles tiles),
+// rounded to A as the partials' sum kernel would store it.
 // A: storage type of w and g (float for FP32/BF16 data, double for FP64).
 constexpr int kWPre = 4, kTPre = 2;
+constexpr int kMaxSplit = 8;  // column ranges per product tile (products below)
 
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void m2_gather_kernel(
     const M2Node *__restrict__ nodes, const int32_t *__restrict__ level, const void *const *data,
     const int32_t *__restrict__ tables, int64_t W, int64_t sample0, int64_t n_samples, int log2m,
     const uint32_t *__restrict__ ltab, int64_t ltab_off, const A *__restrict__ wbuf, int64_t w_row, A *__restrict__ gbuf,
-    int64_t g_row, double *__restrict__ r_out, int64_t r_stride, int tcap) {
+    int64_t g_row, double *__restrict__ r_out, int64_t r_stride, int tcap, const double *__restrict__ cpart,
+    int32_t csplits, int32_t ctiles) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ HashCoeffs coef[3 * kM2MaxChildren];
   __shared__ unsigned long long wmax[kM2MaxChildren], wmax_leaf[kM2MaxChildren];
@@ -438,15 +445,25 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
     pre_j[n_pre++] = j;
   }
   A pre[kWPre];
+  double praw[kMaxSplit];
   uint32_t tpre[kTPre];
   const int n_ent = tab_base[qt];  // slot-table entries of this tensor
   const bool tpre_ok = n_ent <= 256 * kTPre;
   const uint32_t *ltab_node = ltab + (ltab_off + blockIdx.x) * n_samples * tcap;
   auto prefetch = [&](int64_t sp) {
+    if (csplits > 0) {  // at most one non-leaf child (planner): its column partials
+      if (n_pre > 0 && tid < nd.child_dim[pre_j[0]]) {
+        const int64_t tile = nd.child_tile0[pre_j[0]] + (tid >> 6);
 #pragma unroll
-    for (int q = 0; q < kWPre; ++q)
-      if (pre_ok && q < n_pre && tid < nd.child_dim[pre_j[q]])
-        pre[q] = wbuf[sp * w_row + nd.child_w_off[pre_j[q]] + tid];
+        for (int zz = 0; zz < kMaxSplit; ++zz)
+          if (zz < csplits) praw[zz] = cpart[(((int64_t)zz * ctiles + tile) * n_samples + sp) * 64 + (tid & 63)];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < kWPre; ++q)
+        if (pre_ok && q < n_pre && tid < nd.child_dim[pre_j[q]])
+          pre[q] = wbuf[sp * w_row + nd.child_w_off[pre_j[q]] + tid];
+    }
 #pragma unroll
     for (int q = 0; q < kTPre; ++q)
       if (tpre_ok && tid + 256 * q < n_ent) tpre[q] = ltab_node[sp * tcap + tid + 256 * q];
@@ -478,7 +495,16 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
         const int j = pre_j[q];
         double lm = 0.0;
         if (tid < nd.child_dim[j]) {
-          const double x = (double)pre[q];
+          double x;
+          if (csplits > 0) {
+            double v = 0.0;  // the partials' sum kernel's order
+#pragma unroll
+            for (int zz = 0; zz < kMaxSplit; ++zz)
+              if (zz < csplits) v += praw[zz];
+            x = (double)(A)v;
+          } else {
+            x = (double)pre[q];
+          }
           wv[tab_base[j] + tid] = x;
           lm = fabs(x);
         }
@@ -916,6 +942,8 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     hipEvent_t ev = nullptr;
     int rc;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
+    // the children's depth left its products as column partials: summed here
+    const bool cfuse = !export_out && (size_t)d + 1 < P->level_fuse.size() && P->level_fuse[(size_t)d + 1];
     // Samples per block: about 1024 blocks per level (four resident per CU).
     const int64_t nn = (int64_t)P->level_nodes[(size_t)d].size();
     const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, (1024 + nn - 1) / nn));
@@ -924,7 +952,9 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
                        (const void *const *)p->d_data, tables, p->W, c0, n, p->log2m, P->d_ltab, P->level_off[(size_t)d],
                        reinterpret_cast<const A *>(P->d_w), P->w_row,
                        reinterpret_cast<A *>(P->d_g), P->g_row,
-                       export_out ? P->d_r : nullptr, (int64_t)p->n_nets * p->m, P->tcap);
+                       export_out ? P->d_r : nullptr, (int64_t)p->n_nets * p->m, P->tcap,
+                       P->d_part, cfuse ? P->level_splits[(size_t)d + 1] : 0,
+                       cfuse ? (int32_t)P->level_tiles[(size_t)d + 1].size() : 0);
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_SKETCH)) != TN_OK) return rc;
@@ -950,7 +980,7 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
                            gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
       TN_HIP_CHECK(hipGetLastError());
       if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
-      if (z > 1) {  // the partials' sum is timed with the gathers
+      if (z > 1 && !(P->level_fuse[(size_t)d] && !export_out)) {  // the partials' sum is timed with the gathers
         if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
         dim3 g5((unsigned)nt, (unsigned)((n + 3) / 4));
         hipLaunchKernelGGL((m2_reduce_kernel<A>), g5, dim3(256), 0, st, P->d_nodes, tl, nt, z, n, part, wb,
@@ -1156,6 +1186,7 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
         const int u = child_modes[(size_t)k][(size_t)i];
         const int l = c.tensor_of[(size_t)partner[(size_t)u]];
         nd.child_w_off[i] = P->h_nodes[base + (size_t)l].w_off;
+        nd.child_tile0[i] = (int32_t)(base + (size_t)l);  // node index; first tile set below
       }
     }
     gtensor += n.p;
@@ -1177,6 +1208,14 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
     for (int r0 = 0; r0 < nd.rows; r0 += kG16Rows) P->level_tiles[(size_t)nd.depth].push_back({(int32_t)i, r0});
   }
   for (int64_t v : level_cols) P->g_row = std::max(P->g_row, v);
+  {
+    std::vector<int32_t> first_tile(P->h_nodes.size(), -1);
+    for (const auto &lt : P->level_tiles)
+      for (size_t t = 0; t < lt.size(); ++t)
+        if (first_tile[(size_t)lt[t].node] < 0) first_tile[(size_t)lt[t].node] = (int32_t)t;
+    for (M2Node &nd : P->h_nodes)
+      for (int i = 0; i < nd.nchild; ++i) nd.child_tile0[i] = first_tile[(size_t)nd.child_tile0[i]];
+  }
   P->level_off.assign(P->level_nodes.size(), 0);
   for (size_t d = 0; d < P->level_nodes.size(); ++d) {
     P->level_off[d] = (int64_t)P->all_nodes.size();
@@ -1206,11 +1245,30 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
     const int64_t blocks = tiles * ((chunk + kG16Samples - 1) / kG16Samples);
     const int64_t maxc = P->level_maxcols[d];
     int32_t z = 1;
-    while (z < 8 && blocks * z < 512 && maxc >= 16 * cc * z) z *= 2;
+    while (z < kMaxSplit && blocks * z < 512 && maxc >= 16 * cc * z) z *= 2;
     const int64_t kc = ((maxc + z - 1) / z + cc - 1) / cc * cc;
     P->level_splits[d] = z;
     P->level_kcols[d] = (int32_t)kc;
     if (z > 1) part = std::max(part, (size_t)z * (size_t)tiles * (size_t)chunk * kG16Rows);
+  }
+  // A split depth d >= 1 is consumed as partials by the gathers of depth d - 1
+  // when each parent there has at most one non-leaf child, of at most 256
+  // values (it is then loaded into registers ahead of its sample).
+  P->level_fuse.assign(P->level_tiles.size(), 0);
+  for (size_t d = 1; d < P->level_tiles.size(); ++d) {
+    if (P->level_splits[d] <= 1 || P->level_splits[d] > kMaxSplit) continue;
+    bool ok = true;
+    for (int32_t ni : P->level_nodes[d - 1]) {
+      const M2Node &nd = P->h_nodes[(size_t)ni];
+      int nl = 0;
+      for (int i = 0; i < nd.nchild; ++i)
+        if (nd.child_tensor[i] < 0) {
+          ++nl;
+          ok = ok && nd.child_dim[i] <= 256;
+        }
+      ok = ok && nl <= 1;
+    }
+    P->level_fuse[d] = ok ? 1 : 0;
   }
   int rc;
   if ((rc = upload_vec(&p->d_streams, p->h_streams)) != TN_OK) return rc;
