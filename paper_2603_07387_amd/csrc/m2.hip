@@ -818,11 +818,11 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
 }
 
 // Roots (one row): y = sum_col X_o[col] g[col] per sample, a dot product bound
-// by the reads of g, on the vector units in FP64.  Block: four waves, 16
-// samples (four per wave); a lane takes the vectors of W columns W lane + 64 W i,
+// by the reads of g, on the vector units in FP64.  Block: four waves, one
+// sample each; a lane takes the vectors of W columns W lane + 64 W i,
 // then the columns past the last full vector one by one; the wave sums its lanes
 // with a fixed xor tree, so the result does not depend on timing.
-constexpr int kRootSamples = 16;
+constexpr int kRootSamples = 4;
 
 template <typename T, typename A>
 __global__ __launch_bounds__(256) void m2_root_kernel(const M2Node *__restrict__ nodes,
