@@ -277,8 +277,11 @@ def main():
         flops_step = 2.0 * sum(r * c for r, c in prods) * S
         if bf16_products:
             # BF16 matrix cores are ~30x faster than the FP64 ones: the launch is
-            # bound by reading G (FP32, cols x S), X once and writing w.
-            bytes_step = sum(S * c * 4 + r * c * esize + S * r * 4 for r, c in prods)
+            # bound by reading G (cols x S; stored as BF16 for FP32/BF16 data,
+            # FP64 for FP64 data), X once and writing w.
+            gsize = 8 if dtype == "float64" else 2
+            wsize = 8 if dtype == "float64" else 4
+            bytes_step = sum(S * c * gsize + r * c * esize + S * r * wsize for r, c in prods)
             achieved = bytes_step / (sk_ms / a.steps * 1e-3) / 1e9
             roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "m2_gemm16_kernel<BF16>",

@@ -140,12 +140,25 @@ __device__ __forceinline__ uint32_t tsketch(const M2Node &nd, const int32_t *tab
 // col = tid + 256 i; the child index tuple (row-major over the children, the
 // last child fastest) advances by the mixed-radix digits of 256, so the loop
 // divides nothing and every array stays in registers.
-template <typename A, int QT>
+// One value of g in its storage type G: A itself, or (G = uint16_t, BF16
+// products) the BF16 bits of the value rounded to nearest even via FP32, which
+// is the rounding the BF16 product applies to an A-typed g.
+template <typename G, typename A>
+__device__ __forceinline__ void store_g(G *g, size_t i, A v) {
+  if constexpr (sizeof(G) == 2) {
+    const __bf16 b = (__bf16)(float)v;
+    g[i] = *reinterpret_cast<const uint16_t *>(&b);
+  } else {
+    g[i] = v;
+  }
+}
+
+template <typename A, typename G, int QT>
 __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const int32_t *tab_base,
                                                const uint32_t *dtab, const double *wv,
                                                unsigned long long *acc, const int32_t *tab,
                                                const HashCoeffs *coef, uint32_t mask, uint32_t m,
-                                               double sc, double inv_sc, A *g) {
+                                               double sc, double inv_sc, G *g) {
   const int tid = threadIdx.x;
   const uint32_t ncols = (uint32_t)nd.ncols;
   uint32_t dim[QT], step[QT], idx0[QT];
@@ -230,7 +243,7 @@ __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const in
   for (uint32_t col = (uint32_t)tid; col < ncols; col += 256u) {
     const uint32_t h = rs_hash(idx);
     const double r = (double)(long long)acc[h & mask] * inv_sc;
-    g[col] = (A)((h & 0x80000000u) ? -r : r);
+    store_g(g, col, (A)((h & 0x80000000u) ? -r : r));
     advance(idx);
   }
 }
@@ -242,11 +255,11 @@ __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const in
 // broadcast; columns are i0 d1 + i1 as in gather_columns.  The sign of a column
 // is folded into the product before the fixed-point conversion: fma rounds
 // +x and -x symmetrically, so every sketch entry and every g value is bitwise
-// that of gather_columns<A, 2>.
-template <typename A>
+// that of gather_columns<A, G, 2>.
+template <typename A, typename G>
 __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab_base, const uint32_t *dtab,
                                             const double *wv, unsigned long long *acc, uint32_t mask, double sc,
-                                            double inv_sc, A *g) {
+                                            double inv_sc, G *g) {
   const uint32_t tid = threadIdx.x;
   const uint32_t d0 = (uint32_t)nd.child_dim[0], d1 = (uint32_t)nd.child_dim[1];
   const uint32_t R = 256u / d1;
@@ -299,7 +312,7 @@ __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab
         const uint32_t ii = i0 + u * R;
         if (ii < d0) {
           const A r = (A)((double)(long long)a[u] * inv_sc);
-          g[(size_t)ii * d1 + i1] = ((v0[u] ^ v1) & 0x80000000u) ? -r : r;
+          store_g(g, (size_t)ii * d1 + i1, ((v0[u] ^ v1) & 0x80000000u) ? -r : r);
         }
       }
     }
@@ -386,11 +399,11 @@ __global__ __launch_bounds__(kTabThreads) void m2_tables_kernel(const M2Node *__
 constexpr int kWPre = 4, kTPre = 2;
 constexpr int kMaxSplit = 8;  // column ranges per product tile (products below)
 
-template <typename T, typename A>
+template <typename T, typename A, typename G>
 __global__ __launch_bounds__(256) void m2_gather_kernel(
     const M2Node *__restrict__ nodes, const int32_t *__restrict__ level, const void *const *data,
     const int32_t *__restrict__ tables, int64_t W, int64_t sample0, int64_t n_samples, int log2m,
-    const uint32_t *__restrict__ ltab, int64_t ltab_off, const A *__restrict__ wbuf, int64_t w_row, A *__restrict__ gbuf,
+    const uint32_t *__restrict__ ltab, int64_t ltab_off, const A *__restrict__ wbuf, int64_t w_row, G *__restrict__ gbuf,
     int64_t g_row, double *__restrict__ r_out, int64_t r_stride, int tcap, const double *__restrict__ cpart,
     int32_t csplits, int32_t ctiles) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -538,17 +551,17 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
     const double sc = ldexp(1.0, 62 - lgN - e);
     const double inv_sc = ldexp(1.0, -(62 - lgN - e));
 
-    A *g = gbuf + s * g_row + nd.g_off;
+    G *g = gbuf + s * g_row + nd.g_off;
     switch (qt) {
-      case 1: gather_columns<A, 1>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      case 1: gather_columns<A, G, 1>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
       case 2:
         if (nd.child_dim[1] <= 256)
-          gather_pair<A>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
+          gather_pair<A, G>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
         else
-          gather_columns<A, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g);
+          gather_columns<A, G, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g);
         break;
-      case 4: gather_columns<A, 4>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
-      default: gather_columns<A, 8>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      case 4: gather_columns<A, G, 4>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      default: gather_columns<A, G, 8>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
     }
     if (r_out && nd.root) {
       for (uint32_t b = tid; b < m; b += 256)
@@ -629,24 +642,26 @@ struct RawW<uint16_t> {
 constexpr int kG16Rows = 64, kG16Samples = 64, kG16Threads = 256, kG16Pad = 17;
 
 template <typename T, typename A>
-constexpr size_t g16_lds_bytes() {
+constexpr size_t g16_lds_bytes() {  // T: X data, A: g storage
   constexpr size_t tiles = (size_t)2 * kG16Pad * (kG16Rows * sizeof(RawW<T>) + kG16Samples * sizeof(RawW<A>));
   constexpr size_t outb = (size_t)kG16Samples * (kG16Rows + 1) * sizeof(double);
   return tiles > outb ? tiles : outb;
 }
 
-template <typename T, typename A, bool BF>
+// G: storage type of g (A, or BF16 bits with BF).
+template <typename T, typename A, typename G, bool BF>
 __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, int32_t n_tiles,
-    const void *const *data, const A *__restrict__ gbuf, int64_t g_row, int64_t samples,
+    const void *const *data, const G *__restrict__ gbuf, int64_t g_row, int64_t samples,
     A *__restrict__ wbuf, int64_t w_row, double *__restrict__ est, int64_t S, int64_t sample0,
     int32_t kcols, double *__restrict__ part) {
   constexpr int W = RawW<T>::W;
-  static_assert(RawW<A>::W == W, "operand widths differ");
+  static_assert(RawW<G>::W == W, "operand widths differ");
+  static_assert(BF || sizeof(G) == sizeof(A), "BF16 g only with BF16 products");
   constexpr int32_t CC = 16 * W;  // columns per chunk
   constexpr int ROWV = kG16Pad;   // vectors per LDS row (16 + 1 pad)
   using V = RawW<T>;
-  using VA = RawW<A>;
+  using VA = RawW<G>;
   extern __shared__ __align__(16) unsigned char g16_smem[];
   V *Xs = reinterpret_cast<V *>(g16_smem);                                     // [2][64][ROWV]
   VA *Gs = reinterpret_cast<VA *>(g16_smem + (size_t)2 * kG16Rows * ROWV * sizeof(V));  // [2][64][ROWV]
@@ -664,7 +679,7 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
   // loads: slot lv of rows / samples lr + 16 p, p = 0..3
   const int lv = tid & 15, lr = tid >> 4;
   bool xok[4], gok[4];
-  const A *grow[4];
+  const G *grow[4];
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     xok[p] = (int64_t)tl.row0 + lr + 16 * p < rows;
@@ -912,17 +927,19 @@ __global__ void m2_export_kernel(const M2Node *__restrict__ nodes, int32_t n_nod
     out[(s * n_tensors + nd.tensor) * (int64_t)m + b] = x[b];
 }
 
-template <typename T, typename A>
+// G: storage type of g (BF16 bits for BF16 products on FP32 / BF16 data).
+template <typename T, typename A, typename G>
 int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *tables,
              double *est, double *export_out) {
   M2Plan *P = p->m2;
   const size_t lds = (size_t)p->m * 8 + (size_t)P->tcap * 12;
-  auto gk = m2_gather_kernel<T, A>;
-  constexpr size_t g16 = g16_lds_bytes<T, A>();
+  auto gk = m2_gather_kernel<T, A, G>;
+  constexpr size_t g16 = g16_lds_bytes<T, G>();
   if (g16 > 65536) {
-    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
-    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, true>,
+    if constexpr (sizeof(G) == sizeof(A))
+      TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, false>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
+    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
   }
   if (lds > 65536)
@@ -951,7 +968,7 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     hipLaunchKernelGGL(gk, g1, dim3(256), lds, st, P->d_nodes, P->d_level_nodes[(size_t)d],
                        (const void *const *)p->d_data, tables, p->W, c0, n, p->log2m, P->d_ltab, P->level_off[(size_t)d],
                        reinterpret_cast<const A *>(P->d_w), P->w_row,
-                       reinterpret_cast<A *>(P->d_g), P->g_row,
+                       reinterpret_cast<G *>(P->d_g), P->g_row,
                        export_out ? P->d_r : nullptr, (int64_t)p->n_nets * p->m, P->tcap,
                        P->d_part, cfuse ? P->level_splits[(size_t)d + 1] : 0,
                        cfuse ? (int32_t)P->level_tiles[(size_t)d + 1].size() : 0);
@@ -959,25 +976,32 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_SKETCH)) != TN_OK) return rc;
     const void *const *dp = (const void *const *)p->d_data;
-    const A *gb = reinterpret_cast<const A *>(P->d_g);
+    const G *gb = reinterpret_cast<const G *>(P->d_g);
     A *wb = reinterpret_cast<A *>(P->d_w);
     const M2Tile *tl = P->d_level_tiles[(size_t)d];
     const bool bf = (p->flags & TN_FLAG_MFMA_BF16) != 0;
-    if (d == 0 && !bf) {  // roots only, one row each
-      dim3 g3((unsigned)P->level_tiles[0].size(), (unsigned)((n + kRootSamples - 1) / kRootSamples));
-      hipLaunchKernelGGL((m2_root_kernel<T, A>), g3, dim3(256), 0, st, P->d_nodes, tl, dp, gb, P->g_row, n, est,
-                         p->S, c0);
+    if (d == 0 && !bf) {  // roots only, one row each (g in A: without BF16 products)
+      if constexpr (sizeof(G) == sizeof(A)) {
+        dim3 g3((unsigned)P->level_tiles[0].size(), (unsigned)((n + kRootSamples - 1) / kRootSamples));
+        hipLaunchKernelGGL((m2_root_kernel<T, A>), g3, dim3(256), 0, st, P->d_nodes, tl, dp, gb, P->g_row, n, est,
+                           p->S, c0);
+      }
     } else {
       const int32_t nt = (int32_t)P->level_tiles[(size_t)d].size();
       const int32_t z = P->level_splits[(size_t)d];
       dim3 g4((unsigned)nt, (unsigned)((n + kG16Samples - 1) / kG16Samples), (unsigned)z);
       double *part = z > 1 ? P->d_part : nullptr;
-      if (bf)
-        hipLaunchKernelGGL((m2_gemm16_kernel<T, A, true>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt, dp,
-                           gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
-      else
-        hipLaunchKernelGGL((m2_gemm16_kernel<T, A, false>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt, dp,
-                           gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+      if constexpr (sizeof(G) != sizeof(A)) {  // BF16 g: BF16 products only
+        hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, true>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt,
+                           dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+      } else {
+        if (bf)
+          hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, true>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt,
+                             dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+        else
+          hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, false>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt,
+                             dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+      }
       TN_HIP_CHECK(hipGetLastError());
       if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
       if (z > 1 && !(P->level_fuse[(size_t)d] && !export_out)) {  // the partials' sum is timed with the gathers
@@ -1007,9 +1031,14 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
 int m2_run(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, double *est, double *export_out) {
   const int32_t *tables = p->d_injected ? p->d_injected + c0 * p->W : nullptr;
   switch (p->dtype) {
-    case TN_F64: return m2_run_t<double, double>(p, st, c0, n, tables, est, export_out);
-    case TN_F32: return m2_run_t<float, float>(p, st, c0, n, tables, est, export_out);
-    default: return m2_run_t<uint16_t, float>(p, st, c0, n, tables, est, export_out);
+    case TN_F64: return m2_run_t<double, double, double>(p, st, c0, n, tables, est, export_out);
+    case TN_F32:
+      return (p->flags & TN_FLAG_MFMA_BF16) ? m2_run_t<float, float, uint16_t>(p, st, c0, n, tables, est, export_out)
+                                            : m2_run_t<float, float, float>(p, st, c0, n, tables, est, export_out);
+    default:
+      return (p->flags & TN_FLAG_MFMA_BF16)
+                 ? m2_run_t<uint16_t, float, uint16_t>(p, st, c0, n, tables, est, export_out)
+                 : m2_run_t<uint16_t, float, float>(p, st, c0, n, tables, est, export_out);
   }
 }
 
