@@ -95,11 +95,11 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
   const int tid = threadIdx.x;
   // Twiddles: staged in LDS after z when the launch provides the room (every
   // butterfly pass reads them; from the global table each pass would wait on
-  // a cache round trip).
+  // a cache round trip).  With them, z and the twiddles are padded (pad32).
   const A2 *twl = tw;
   if constexpr (TWL) {
-    A2 *t = z + M;
-    for (int j = tid; j < M / 2; j += 256) t[j] = tw[j];
+    A2 *t = z + pad32(M);
+    for (int j = tid; j < M / 2; j += 256) t[pad32(j)] = tw[j];
     twl = t;  // the first barrier below publishes it
   }
 
@@ -115,15 +115,15 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
       A v1 = 0, v2 = 0;
       for (int sl = a0; sl < a1; ++sl) v1 += y[(int64_t)sl * M + b];
       for (int sl = a1; sl < b1; ++sl) v2 += y[(int64_t)sl * M + b];
-      z[bitrev<LOG2M>(b)] = A2{v1, v2};
+      z[TWL ? pad32(bitrev<LOG2M>(b)) : bitrev<LOG2M>(b)] = A2{v1, v2};
     }
     __syncthreads();
-    fft_lds<A, LOG2M>(z, twl);
+    fft_lds<A, LOG2M, TWL>(z, twl);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int j = tid + 256 * c;
       if (j < H) {
-        const A2 za = z[j], zb = z[(M - j) & (M - 1)];
+        const A2 za = z[TWL ? pad32(j) : j], zb = z[TWL ? pad32((M - j) & (M - 1)) : (M - j) & (M - 1)];
         const double ar = za.x, ai = za.y, br = zb.x, bi = -(double)zb.y;  // B = conj(Z[-j])
         double qr, qi;
         if (pair) {
@@ -341,10 +341,12 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const v
               int64_t n_slots, int64_t samples, int64_t sample0, int64_t S, const void *tw,
               double *est, hipStream_t st) {
   using A2 = typename Cplx<A>::type;
-  // z (m points) and, when the total stays within 64 KB, the m/2 twiddles
-  constexpr bool TWL = LOG2M >= 1 && (sizeof(A2) << LOG2M) * 3 / 2 <= 65536;
+  // z (m points) and, when the total stays within 64 KB, the m/2 twiddles, both
+  // with one spare element per 32 (bank spread)
+  constexpr size_t zt = sizeof(A2) * (size_t)((1 << LOG2M) + (1 << LOG2M) / 32 + (1 << LOG2M) / 2 + (1 << LOG2M) / 64 + 2);
+  constexpr bool TWL = LOG2M >= 1 && zt <= 65536;
   auto kern = m1_combine_kernel<A, LOG2M, TWL>;
-  const size_t lds = TWL ? (sizeof(A2) << LOG2M) * 3 / 2 : sizeof(A2) << LOG2M;
+  const size_t lds = TWL ? zt : sizeof(A2) << LOG2M;
   if (lds > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));

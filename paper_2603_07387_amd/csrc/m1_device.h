@@ -331,11 +331,17 @@ struct Cplx<double> {
 // radix-2^2 group through both stages in registers (the same butterflies and
 // twiddles as two radix-2 passes), which halves the barriers and LDS passes; an
 // odd stage count starts with one single stage.
-template <typename A, int LOG2M>
+// PAD: z and tw are held with one spare element after every 32 (element e at
+// pad32(e)), which spreads the strided accesses of the first passes, the
+// bit-reversed loads and the twiddle reads over the LDS banks.
+__device__ __forceinline__ constexpr int pad32(int e) { return e + (e >> 5); }
+
+template <typename A, int LOG2M, bool PAD = false>
 __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
                                         const typename Cplx<A>::type *__restrict__ tw) {
   constexpr int M = 1 << LOG2M;
   using A2 = typename Cplx<A>::type;
+  auto P = [](int e) { return PAD ? pad32(e) : e; };
   auto bfly = [](A2 &za, A2 &zb, const A2 w) {
     const A tr = w.x * zb.x - w.y * zb.y;
     const A ti = w.x * zb.y + w.y * zb.x;
@@ -345,10 +351,10 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
   int lg = 1;
   if constexpr ((LOG2M & 1) != 0) {
     for (int q = threadIdx.x; q < M / 2; q += 256) {
-      A2 za = z[2 * q], zb = z[2 * q + 1];
+      A2 za = z[P(2 * q)], zb = z[P(2 * q + 1)];
       bfly(za, zb, tw[0]);
-      z[2 * q] = za;
-      z[2 * q + 1] = zb;
+      z[P(2 * q)] = za;
+      z[P(2 * q + 1)] = zb;
     }
     __syncthreads();
     lg = 2;
@@ -359,16 +365,16 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
     for (int q = threadIdx.x; q < M / 4; q += 256) {
       const int k = q & (h - 1);
       const int base = ((q >> (lg - 1)) << (lg + 1)) + k;
-      A2 z0 = z[base], z1 = z[base + h], z2 = z[base + 2 * h], z3 = z[base + 3 * h];
-      const A2 w1 = tw[k << (LOG2M - lg)];
+      A2 z0 = z[P(base)], z1 = z[P(base + h)], z2 = z[P(base + 2 * h)], z3 = z[P(base + 3 * h)];
+      const A2 w1 = tw[P(k << (LOG2M - lg))];
       bfly(z0, z1, w1);  // stage lg: (base, base + h), (base + 2h, base + 3h)
       bfly(z2, z3, w1);
-      bfly(z0, z2, tw[k << (LOG2M - lg - 1)]);  // stage lg + 1: (base, base + 2h), (base + h, base + 3h)
-      bfly(z1, z3, tw[(k + h) << (LOG2M - lg - 1)]);
-      z[base] = z0;
-      z[base + h] = z1;
-      z[base + 2 * h] = z2;
-      z[base + 3 * h] = z3;
+      bfly(z0, z2, tw[P(k << (LOG2M - lg - 1))]);  // stage lg + 1: (base, base + 2h), (base + h, base + 3h)
+      bfly(z1, z3, tw[P((k + h) << (LOG2M - lg - 1))]);
+      z[P(base)] = z0;
+      z[P(base + h)] = z1;
+      z[P(base + 2 * h)] = z2;
+      z[P(base + 3 * h)] = z3;
     }
     __syncthreads();
   }
