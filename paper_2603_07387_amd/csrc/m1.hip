@@ -186,28 +186,28 @@ __global__ __launch_bounds__(256) void m1_big_cols_kernel(const int32_t *__restr
                                                           const typename Cplx<A>::type *__restrict__ tw,
                                                           typename Cplx<A>::type *__restrict__ cbuf) {
   using A2 = typename Cplx<A>::type;
-  __shared__ A2 z[kBigCols][kBigN2];
-  __shared__ A2 tw2[kBigN2 / 2];
+  __shared__ A2 z[kBigCols][kBigN2 + kBigN2 / 32];  // padded (pad32)
+  __shared__ A2 tw2[kBigN2 / 2 + kBigN2 / 64];
   const uint32_t m = 1u << log2m, n1 = m / kBigN2;
   const int64_t k = blockIdx.x, s = blockIdx.y;
   const uint32_t b1_0 = blockIdx.z * kBigCols;
   const int tid = threadIdx.x;
-  if (tid < kBigN2 / 2) tw2[tid] = tw[(uint32_t)tid * n1];  // w_n2^t = w_m^(t n1)
+  if (tid < kBigN2 / 2) tw2[pad32(tid)] = tw[(uint32_t)tid * n1];  // w_n2^t = w_m^(t n1)
   const A *y = ybuf + s * n_slots * (int64_t)m;
   // column b1 = b1_0 + c: y[b1 + n1 b2], b2 = tid, summed over the tensor's slots
 #pragma unroll 4
   for (int c = 0; c < kBigCols; ++c) {
     A v = 0;
     for (int sl = tslot[k]; sl < tslot[k + 1]; ++sl) v += y[(int64_t)sl * m + b1_0 + c + (int64_t)n1 * tid];
-    z[c][bitrev<8>(tid)] = A2{v, (A)0};
+    z[c][pad32(bitrev<8>(tid))] = A2{v, (A)0};
   }
   __syncthreads();
-  for (int c = 0; c < kBigCols; ++c) fft_lds<A, 8>(z[c], tw2);  // ends with a barrier
+  for (int c = 0; c < kBigCols; ++c) fft_lds<A, 8, true>(z[c], tw2);  // ends with a barrier
   // C[j2][b1] = Z_b1[j2] w_m^(b1 j2); thread j2 writes kBigCols consecutive b1
   A2 *out = cbuf + (s * n_tensors + k) * (int64_t)m + (int64_t)tid * n1 + b1_0;
 #pragma unroll 4
   for (int c = 0; c < kBigCols; ++c) {
-    const A2 v = z[c][tid], w = twiddle_at(tw, (b1_0 + c) * (uint32_t)tid, m);
+    const A2 v = z[c][pad32(tid)], w = twiddle_at(tw, (b1_0 + c) * (uint32_t)tid, m);
     out[c] = A2{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
   }
 }
@@ -220,24 +220,24 @@ __global__ __launch_bounds__(256) void m1_big_rows_kernel(const NetDesc *__restr
   using A2 = typename Cplx<A>::type;
   constexpr int N1 = 1 << LOG2N1;
   constexpr uint32_t M = (uint32_t)N1 * kBigN2;
-  __shared__ A2 z[N1];
-  __shared__ A2 tw1[N1 / 2];
+  __shared__ A2 z[N1 + N1 / 32];  // padded (pad32)
+  __shared__ A2 tw1[N1 / 2 + N1 / 64];
   __shared__ double red[4];
   const NetDesc nd = nets[blockIdx.x];
   const int64_t s = blockIdx.y;
   const int tid = threadIdx.x;
-  if (tid < N1 / 2) tw1[tid] = tw[(uint32_t)tid * kBigN2];  // w_n1^t = w_m^(t n2)
+  if (tid < N1 / 2) tw1[pad32(tid)] = tw[(uint32_t)tid * kBigN2];  // w_n1^t = w_m^(t n2)
   double acc = 0.0;
   for (int r = 0; r < kBigRows; ++r) {
     const uint32_t j2 = blockIdx.z * kBigRows + r;
     double pr = 1.0, pi = 0.0;
     for (int k = nd.t0; k < nd.t1; ++k) {
       __syncthreads();  // the previous transform's readers are done (and tw1 is written)
-      if (tid < N1) z[bitrev<LOG2N1>(tid)] = cbuf[(s * n_tensors + k) * (int64_t)M + (int64_t)j2 * N1 + tid];
+      if (tid < N1) z[pad32(bitrev<LOG2N1>(tid))] = cbuf[(s * n_tensors + k) * (int64_t)M + (int64_t)j2 * N1 + tid];
       __syncthreads();
-      fft_lds<A, LOG2N1>(z, tw1);
+      fft_lds<A, LOG2N1, true>(z, tw1);
       if (tid < N1) {
-        const double yr = z[tid].x, yi = z[tid].y;
+        const double yr = z[pad32(tid)].x, yi = z[pad32(tid)].y;
         const double nr = pr * yr - pi * yi;
         pi = pr * yi + pi * yr;
         pr = nr;
