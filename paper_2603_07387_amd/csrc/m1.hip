@@ -31,11 +31,12 @@ using namespace m1dev;
 // One block streams one slot and accumulates the sketches of SB samples (see
 // scatter_slot), then writes them out as floating point.
 // Blocks of 256 threads with one bank, 512 with two (twice the accumulator LDS
-// per block, the same waves per CU).
+// per block, the same waves per CU); NT = 1024 when one block fills a CU's LDS
+// (large m or many samples per pass), so that the CU still runs 16 waves.
 // RANGED (m above kMaxLog2Acc buckets): blockIdx.z selects the range of
 // 2^log2acc buckets the block accumulates (one bank, one sample per pass).
-template <typename T, typename A, int SB, int BANKS, bool RANGED = false>
-__global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
+template <typename T, typename A, int SB, int BANKS, bool RANGED = false, int NT = 256 * BANKS>
+__global__ __launch_bounds__(NT) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
     int64_t samples, int log2m, int log2acc, int64_t n_slots, A *__restrict__ ybuf) {
@@ -57,7 +58,6 @@ __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
   unsigned long long *s_max = reinterpret_cast<unsigned long long *>(smem + acc_end);  // [2]
   uint32_t *colt = reinterpret_cast<uint32_t *>(smem + acc_end + 16);                  // [SB][L]
   uint32_t *rowt = colt + SB * sl.L;                                                   // [SB][rows]
-  constexpr int NT = 256 * BANKS;
   for (int i = tid; i < (int)(acc_bytes / 8); i += NT) acc[i] = 0ull;
   if (tid < 2) s_max[tid] = 0ull;
   const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
@@ -76,18 +76,23 @@ __global__ __launch_bounds__(256 * BANKS) void m1_scatter_kernel(
   }
 }
 
-template <typename A, int LOG2M, bool TWL>
-__global__ __launch_bounds__(256) void m1_combine_kernel(
+// NTH threads: 256, or 1024 for m >= 8192 (a block then fills most of a
+// CU's LDS, and the per-thread share of the half spectrum stays small).
+template <typename A, int LOG2M, bool TWL, int NTH = 256>
+__global__ __launch_bounds__(NTH) void m1_combine_kernel(
     const NetDesc *__restrict__ nets, const int32_t *__restrict__ tslot,
     const A *__restrict__ ybuf, int64_t n_slots, int64_t sample0, int64_t S,
     const typename Cplx<A>::type *__restrict__ tw, double *__restrict__ est) {
   using A2 = typename Cplx<A>::type;
   constexpr int M = 1 << LOG2M;
   constexpr int H = M / 2 + 1;
-  constexpr int NC = (H + 255) / 256;
+  constexpr int NC = (H + NTH - 1) / NTH;
+  // sketch points per thread and load round: all of a round's loads are in
+  // flight together
+  constexpr int G = M >= 8 * NTH ? 8 : (M >= NTH ? M / NTH : 1);
   extern __shared__ __align__(16) unsigned char smem[];
   A2 *z = reinterpret_cast<A2 *>(smem);
-  __shared__ double red[4];
+  __shared__ double red[NTH / 64];
 
   const NetDesc nd = nets[blockIdx.x];
   const int64_t s = blockIdx.y;
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
   const A2 *twl = tw;
   if constexpr (TWL) {
     A2 *t = z + pad32(M);
-    for (int j = tid; j < M / 2; j += 256) t[pad32(j)] = tw[j];
+    for (int j = tid; j < M / 2; j += NTH) t[pad32(j)] = tw[j];
     twl = t;  // the first barrier below publishes it
   }
 
@@ -111,17 +116,36 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
     const bool pair = (k + 1) < nd.t1;
     const int a0 = tslot[k], a1 = tslot[k + 1];
     const int b1 = pair ? tslot[k + 2] : a1;
-    for (int b = tid; b < M; b += 256) {
-      A v1 = 0, v2 = 0;
-      for (int sl = a0; sl < a1; ++sl) v1 += y[(int64_t)sl * M + b];
-      for (int sl = a1; sl < b1; ++sl) v2 += y[(int64_t)sl * M + b];
-      z[TWL ? pad32(bitrev<LOG2M>(b)) : bitrev<LOG2M>(b)] = A2{v1, v2};
+    for (int b0 = 0; b0 < M; b0 += NTH * G) {
+      A v1[G], v2[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) v1[g] = v2[g] = 0;
+      // (b < M only fails when M < NTH: those threads read point 0 and store nothing)
+      for (int sl = a0; sl < a1; ++sl) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int b = b0 + g * NTH + tid;
+          v1[g] += y[(int64_t)sl * M + (b < M ? b : 0)];
+        }
+      }
+      for (int sl = a1; sl < b1; ++sl) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int b = b0 + g * NTH + tid;
+          v2[g] += y[(int64_t)sl * M + (b < M ? b : 0)];
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int b = b0 + g * NTH + tid;
+        if (b < M) z[TWL ? pad32(bitrev<LOG2M>(b)) : bitrev<LOG2M>(b)] = A2{v1[g], v2[g]};
+      }
     }
     __syncthreads();
-    fft_lds<A, LOG2M, TWL>(z, twl);
+    fft_lds<A, LOG2M, TWL, NTH>(z, twl);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const int j = tid + 256 * c;
+      const int j = tid + NTH * c;
       if (j < H) {
         const A2 za = z[TWL ? pad32(j) : j], zb = z[TWL ? pad32((M - j) & (M - 1)) : (M - j) & (M - 1)];
         const double ar = za.x, ai = za.y, br = zb.x, bi = -(double)zb.y;  // B = conj(Z[-j])
@@ -147,10 +171,10 @@ __global__ __launch_bounds__(256) void m1_combine_kernel(
   double part = 0.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const int j = tid + 256 * c;
+    const int j = tid + NTH * c;
     if (j < H) part += ((j == 0 || 2 * j == M) ? 1.0 : 2.0) * pr[c];
   }
-  const double tot = block_sum_256(part, red);
+  const double tot = block_sum<NTH>(part, red);
   if (tid == 0) est[(int64_t)blockIdx.x * S + sample0 + s] = tot / (double)M;
 }
 
@@ -306,19 +330,25 @@ __global__ void twiddle_kernel(int64_t m, typename Cplx<A>::type *out) {
   }
 }
 
+constexpr size_t kWideLds = 81920;
+
 template <typename T, typename A, int SB>
 int scatter_sb(const M1Launch &L, hipStream_t st) {
   const bool ranged = L.log2m > kMaxLog2Acc;
   if (ranged && (SB != 1 || L.banks != 1))
     return set_error(TN_ERR_ARG, "scatter: m = 2^%d takes one bank and one sample per pass", L.log2m);
-  auto kern = ranged ? m1_scatter_kernel<T, A, SB, 1, true>
+  // One block per CU when its LDS exceeds half a CU's: then 1024 threads.
+  const bool wide = ranged || L.lds_bytes > kWideLds;
+  auto kern = ranged ? m1_scatter_kernel<T, A, SB, 1, true, 1024>
+              : wide ? (L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2, false, 1024>
+                                     : m1_scatter_kernel<T, A, SB, 1, false, 1024>)
                      : (L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2> : m1_scatter_kernel<T, A, SB, 1>);
   if (L.lds_bytes > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)L.lds_bytes));
   dim3 grid((unsigned)L.n_slots, (unsigned)((L.samples + SB - 1) / SB),
             ranged ? 1u << (L.log2m - kMaxLog2Acc) : 1u);
-  hipLaunchKernelGGL(kern, grid, dim3(256 * L.banks), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
+  hipLaunchKernelGGL(kern, grid, dim3(wide ? 1024 : 256 * L.banks), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
                      L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, reinterpret_cast<A *>(L.ybuf));
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
@@ -345,13 +375,14 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const v
   // with one spare element per 32 (bank spread)
   constexpr size_t zt = sizeof(A2) * (size_t)((1 << LOG2M) + (1 << LOG2M) / 32 + (1 << LOG2M) / 2 + (1 << LOG2M) / 64 + 2);
   constexpr bool TWL = LOG2M >= 1 && zt <= 65536;
-  auto kern = m1_combine_kernel<A, LOG2M, TWL>;
+  constexpr int NTH = LOG2M >= 13 ? 1024 : 256;
+  auto kern = m1_combine_kernel<A, LOG2M, TWL, NTH>;
   const size_t lds = TWL ? zt : sizeof(A2) << LOG2M;
   if (lds > 65536)
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
   dim3 grid((unsigned)n_nets, (unsigned)samples);
-  hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, nets, tslot,
+  hipLaunchKernelGGL(kern, grid, dim3(NTH), lds, st, nets, tslot,
                      reinterpret_cast<const A *>(ybuf), n_slots, sample0, S,
                      reinterpret_cast<const A2 *>(tw), est);
   TN_HIP_CHECK(hipGetLastError());

@@ -245,12 +245,21 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
     const V __attribute__((address_space(1))) *Xv =
         (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X);
     const uint32_t NV = N / VEC;
-    for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
-      // Unconditional loads (index clamped into the slot) keep all UNROLL loads
-      // in flight; out-of-range lanes are masked when the values are used.
-      V buf[UNROLL];
+    // Unconditional loads (index clamped into the slot) keep all UNROLL loads
+    // in flight; out-of-range lanes are masked when the values are used.
+    // Blocks of 512 or more threads (few blocks per CU: their LDS is large)
+    // issue the next iteration's loads before this iteration's adds, so the
+    // load latency hides behind the LDS atomics; small blocks overlap with
+    // other blocks instead and keep the registers.
+    constexpr bool PREFETCH = NT >= 512;
+    V buf[UNROLL], nxt[UNROLL];
+    if constexpr (PREFETCH) {
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) buf[u] = Xv[min(v0 + u * NT + tid, NV - 1)];
+      for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
+    }
+    for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
       double lmax = 0.0;
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
@@ -259,6 +268,10 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
         for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
       }
       update_scale(lmax);
+      if (PREFETCH && v0 + NT * UNROLL < NV) {  // uniform over the block
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
+      }
       uint32_t rr[UNROLL], cc[UNROLL];
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
@@ -336,7 +349,7 @@ struct Cplx<double> {
 // bit-reversed loads and the twiddle reads over the LDS banks.
 __device__ __forceinline__ constexpr int pad32(int e) { return e + (e >> 5); }
 
-template <typename A, int LOG2M, bool PAD = false>
+template <typename A, int LOG2M, bool PAD = false, int NTH = 256>
 __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
                                         const typename Cplx<A>::type *__restrict__ tw) {
   constexpr int M = 1 << LOG2M;
@@ -350,7 +363,7 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
   };
   int lg = 1;
   if constexpr ((LOG2M & 1) != 0) {
-    for (int q = threadIdx.x; q < M / 2; q += 256) {
+    for (int q = threadIdx.x; q < M / 2; q += NTH) {
       A2 za = z[P(2 * q)], zb = z[P(2 * q + 1)];
       bfly(za, zb, tw[0]);
       z[P(2 * q)] = za;
@@ -362,7 +375,7 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
 #pragma unroll 1
   for (; lg < LOG2M; lg += 2) {
     const int h = 1 << (lg - 1);
-    for (int q = threadIdx.x; q < M / 4; q += 256) {
+    for (int q = threadIdx.x; q < M / 4; q += NTH) {
       const int k = q & (h - 1);
       const int base = ((q >> (lg - 1)) << (lg + 1)) + k;
       A2 z0 = z[P(base)], z1 = z[P(base + h)], z2 = z[P(base + 2 * h)], z3 = z[P(base + 3 * h)];
@@ -389,17 +402,24 @@ __device__ __forceinline__ int bitrev(int b) {
   }
 }
 
-__device__ __forceinline__ double block_sum_256(double v, double *red) {
+// Block sum of one double per thread (NTH threads, red holds NTH / 64);
+// the total is returned to thread 0.
+template <int NTH = 256>
+__device__ __forceinline__ double block_sum(double v, double *red) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (lane == 0) red[wv] = v;
   __syncthreads();
   double t = 0.0;
-  if (threadIdx.x == 0) t = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < NTH / 64; ++w) t += red[w];
+  }
   __syncthreads();
   return t;
 }
+__device__ __forceinline__ double block_sum_256(double v, double *red) { return block_sum<256>(v, red); }
 
 }  // namespace m1dev
 }  // namespace tn
