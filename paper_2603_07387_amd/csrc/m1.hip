@@ -181,18 +181,31 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
 // ---------------------------------------------------------------------------
 // Combine when the m-point FFT does not fit in LDS (m = 2^14 with FP64 data,
 // m >= 2^15):
-// the same estimate (1/m) Re sum_j prod_k Y_k[j], with each Y_k = F y_k taken in
-// two passes through HBM.  With m = n1 n2 (n2 = 256), b = b1 + n1 b2 and
-// j = j2 + n2 j1,
-//   Y[j2 + n2 j1] = sum_b1 w_n1^(b1 j1) w_m^(b1 j2) sum_b2 y[b1 + n1 b2] w_n2^(b2 j2),
-// w_n = exp(-2 pi i / n).  Pass 1 (per tensor and sample): the n2-point DFTs
-// over b2 of each column b1, times w_m^(b1 j2), stored transposed as
-// C[j2][b1].  Pass 2 (per network and sample, rows j2 split over blocks): the
-// n1-point DFT of each row of every tensor gives Y at the n1 frequencies
-// j2 + n2 j1; their product over the network's tensors, in FP64, is summed
-// over the row.  Every frequency is visited once, so the order of the sum is
-// fixed and the result matches the in-LDS combine up to FFT rounding.
-constexpr int kBigN2 = 256, kBigCols = 8, kBigRows = 4;
+// the same estimate (1/m) Re sum_j prod_k Y_k[j], with the spectra taken in two
+// passes through HBM.  As in the in-LDS combine, the tensors of a network go
+// in pairs, z = y_a + i y_b (an odd one out with y_b = 0), and the pair's
+// product spectrum is Y_a Y_b = (Z[j]^2 - conj(Z[-j])^2) / 4i.  With
+// m = n1 n2 (n2 = 256), b = b1 + n1 b2 and j = j2 + n2 j1,
+//   Z[j2 + n2 j1] = sum_b1 w_n1^(b1 j1) w_m^(b1 j2) sum_b2 z[b1 + n1 b2] w_n2^(b2 j2),
+// w_n = exp(-2 pi i / n).
+// Pass 1 (per pair, sample and run of columns b1): the n2-point DFTs over b2
+// of the columns, all in one batched LDS transform, times w_m^(b1 j2), stored
+// transposed as C[j2][b1].
+// Pass 2 (per network, sample and mirror pair of rows): -(j2 + n2 j1) mod m is
+// (n2 - j2) + n2 (n1 - 1 - j1) for j2 > 0, so row j2 holds the negated
+// frequencies of row n2 - j2.  A block takes rows j2 and n2 - j2 (j2 in
+// 1..127), or the self-mirrored rows 0 and 128, of every pair of the network,
+// takes their n1-point DFTs in one batched LDS transform, and sums
+// prod_pairs (Y_a Y_b)[j] over its frequencies in FP64: 2 Re over row j2 (row
+// n2 - j2 holds the conjugates), Re over both self-mirrored rows.  Every
+// frequency is visited once and the blocks' sums are added in a fixed order,
+// so the result matches the in-LDS combine up to FFT rounding.
+constexpr int kBigN2 = 256, kBigRowPairs = kBigN2 / 2;
+static_assert(kBigRowPairs == kBigPartials, "one partial sum per row block");
+// LDS stride between the transforms of a batch: pad32(256) and one more
+// element, so that reading the same point of consecutive transforms (the
+// transposed store) falls into distinct banks.
+constexpr int kBigStr = kBigN2 + kBigN2 / 32 + 1;
 
 // w_m^e from the half table tw[j] = w_m^j, j < m/2.
 template <typename A2>
@@ -203,74 +216,153 @@ __device__ __forceinline__ A2 twiddle_at(const A2 *__restrict__ tw, uint32_t e, 
   return A2{-t.x, -t.y};
 }
 
+// Columns per pass-1 block: one 128-byte line of each input row per block
+// for FP32 sketches, 256 bytes for FP64 (the transforms then fill 68 KB of LDS).
+template <typename A>
+constexpr int big_cols() { return sizeof(A) == 4 ? 32 : 16; }
+template <typename A>
+constexpr size_t big_cols_lds() {
+  return sizeof(typename Cplx<A>::type) * (size_t)(big_cols<A>() * kBigStr + kBigN2 / 2 + kBigN2 / 64);
+}
+
 template <typename A>
 __global__ __launch_bounds__(256) void m1_big_cols_kernel(const int32_t *__restrict__ tslot,
-                                                          const A *__restrict__ ybuf, int64_t n_slots,
-                                                          int64_t n_tensors, int log2m,
+                                                          const int32_t *__restrict__ pairs, int64_t n_pairs,
+                                                          const A *__restrict__ ybuf, int64_t n_slots, int log2m,
                                                           const typename Cplx<A>::type *__restrict__ tw,
                                                           typename Cplx<A>::type *__restrict__ cbuf) {
   using A2 = typename Cplx<A>::type;
-  __shared__ A2 z[kBigCols][kBigN2 + kBigN2 / 32];  // padded (pad32)
-  __shared__ A2 tw2[kBigN2 / 2 + kBigN2 / 64];
+  constexpr int CB = big_cols<A>();    // columns b1 of this block
+  constexpr int RS = 256 / CB;         // b2 = r0 + RS i: the thread's points of its column
+  constexpr int RPT = kBigN2 / RS;     // points per thread
+  constexpr int G = 8;                 // loads in flight per tensor and round
+  static_assert(RPT % G == 0, "load rounds");
+  extern __shared__ __align__(16) unsigned char smem[];
+  A2 *z = reinterpret_cast<A2 *>(smem);
+  A2 *tw2 = z + CB * kBigStr;
   const uint32_t m = 1u << log2m, n1 = m / kBigN2;
-  const int64_t k = blockIdx.x, s = blockIdx.y;
-  const uint32_t b1_0 = blockIdx.z * kBigCols;
-  const int tid = threadIdx.x;
+  const int64_t pr = blockIdx.x, s = blockIdx.y;
+  const uint32_t b1_0 = blockIdx.z * CB;
+  const int tid = threadIdx.x, c = tid % CB, r0 = tid / CB;
   if (tid < kBigN2 / 2) tw2[pad32(tid)] = tw[(uint32_t)tid * n1];  // w_n2^t = w_m^(t n1)
-  const A *y = ybuf + s * n_slots * (int64_t)m;
-  // column b1 = b1_0 + c: y[b1 + n1 b2], b2 = tid, summed over the tensor's slots
-#pragma unroll 4
-  for (int c = 0; c < kBigCols; ++c) {
-    A v = 0;
-    for (int sl = tslot[k]; sl < tslot[k + 1]; ++sl) v += y[(int64_t)sl * m + b1_0 + c + (int64_t)n1 * tid];
-    z[c][pad32(bitrev<8>(tid))] = A2{v, (A)0};
+  const int ta = pairs[2 * pr], tb = pairs[2 * pr + 1];
+  const int a0 = tslot[ta], a1 = tslot[ta + 1];
+  const int bb0 = tb >= 0 ? tslot[tb] : 0, bb1 = tb >= 0 ? tslot[tb + 1] : 0;
+  const A *y = ybuf + s * n_slots * (int64_t)m + b1_0 + c;
+  // z[b1 + n1 b2] = y_a + i y_b (each summed over its tensor's slots), stored
+  // bit-reversed for the transform of column c
+  for (int i0 = 0; i0 < RPT; i0 += G) {
+    A va[G], vb[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) va[g] = vb[g] = 0;
+    for (int sl = a0; sl < a1; ++sl) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) va[g] += y[(int64_t)sl * m + (int64_t)n1 * (r0 + RS * (i0 + g))];
+    }
+    for (int sl = bb0; sl < bb1; ++sl) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) vb[g] += y[(int64_t)sl * m + (int64_t)n1 * (r0 + RS * (i0 + g))];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) z[c * kBigStr + pad32(bitrev<8>(r0 + RS * (i0 + g)))] = A2{va[g], vb[g]};
   }
   __syncthreads();
-  for (int c = 0; c < kBigCols; ++c) fft_lds<A, 8, true>(z[c], tw2);  // ends with a barrier
-  // C[j2][b1] = Z_b1[j2] w_m^(b1 j2); thread j2 writes kBigCols consecutive b1
-  A2 *out = cbuf + (s * n_tensors + k) * (int64_t)m + (int64_t)tid * n1 + b1_0;
+  fft_lds_batch<A, 8, kBigStr, 256>(z, tw2, CB);  // ends with a barrier
+  // C[j2][b1] = Z_b1[j2] w_m^(b1 j2): lanes of consecutive b1 write one
+  // contiguous run per j2
+  A2 *out = cbuf + (s * n_pairs + pr) * (int64_t)m + b1_0 + c;
+  const uint32_t b1 = b1_0 + c;
 #pragma unroll 4
-  for (int c = 0; c < kBigCols; ++c) {
-    const A2 v = z[c][pad32(tid)], w = twiddle_at(tw, (b1_0 + c) * (uint32_t)tid, m);
-    out[c] = A2{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+  for (int i = 0; i < RPT; ++i) {
+    const int j2 = r0 + RS * i;
+    const A2 v = z[c * kBigStr + pad32(j2)], w = twiddle_at(tw, b1 * (uint32_t)j2, m);
+    out[(int64_t)j2 * n1] = A2{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
   }
 }
 
+// Pairs per pass-2 round: 2 rows each, KP * 2 transforms in LDS (34 KB).
+template <typename A>
+constexpr int big_rows_pairs() { return sizeof(A) == 4 ? 8 : 4; }
+
 template <typename A, int LOG2N1>
-__global__ __launch_bounds__(256) void m1_big_rows_kernel(const NetDesc *__restrict__ nets,
+__global__ __launch_bounds__(256) void m1_big_rows_kernel(const int32_t *__restrict__ pair0,
+                                                          const int32_t *__restrict__ pairs, int64_t n_pairs,
                                                           const typename Cplx<A>::type *__restrict__ cbuf,
-                                                          int64_t n_tensors, const typename Cplx<A>::type *__restrict__ tw,
+                                                          const typename Cplx<A>::type *__restrict__ tw,
                                                           double *__restrict__ partial) {
   using A2 = typename Cplx<A>::type;
   constexpr int N1 = 1 << LOG2N1;
   constexpr uint32_t M = (uint32_t)N1 * kBigN2;
-  __shared__ A2 z[N1 + N1 / 32];  // padded (pad32)
+  constexpr int KP = big_rows_pairs<A>();
+  constexpr int STR = N1 + N1 / 32 + 1;
+  constexpr int NL = 2 * KP * N1 / 256;  // loads per thread and round
+  static_assert(NL >= 1 && (2 * KP * N1) % 256 == 0, "load rounds");
+  __shared__ A2 z[2 * KP * STR];
   __shared__ A2 tw1[N1 / 2 + N1 / 64];
   __shared__ double red[4];
-  const NetDesc nd = nets[blockIdx.x];
+  const int net = blockIdx.x;
   const int64_t s = blockIdx.y;
-  const int tid = threadIdx.x;
+  const int rp = blockIdx.z, tid = threadIdx.x;
+  const int rowA = rp == 0 ? 0 : rp, rowB = rp == 0 ? kBigN2 / 2 : kBigN2 - rp;
   if (tid < N1 / 2) tw1[pad32(tid)] = tw[(uint32_t)tid * kBigN2];  // w_n1^t = w_m^(t n2)
-  double acc = 0.0;
-  for (int r = 0; r < kBigRows; ++r) {
-    const uint32_t j2 = blockIdx.z * kBigRows + r;
-    double pr = 1.0, pi = 0.0;
-    for (int k = nd.t0; k < nd.t1; ++k) {
-      __syncthreads();  // the previous transform's readers are done (and tw1 is written)
-      if (tid < N1) z[pad32(bitrev<LOG2N1>(tid))] = cbuf[(s * n_tensors + k) * (int64_t)M + (int64_t)j2 * N1 + tid];
-      __syncthreads();
-      fft_lds<A, LOG2N1, true>(z, tw1);
-      if (tid < N1) {
-        const double yr = z[pad32(tid)].x, yi = z[pad32(tid)].y;
-        const double nr = pr * yr - pi * yi;
-        pi = pr * yi + pi * yr;
-        pr = nr;
+  const int p0 = pair0[net], p1 = pair0[net + 1];
+  double pr1 = 1.0, pi1 = 0.0, pr2 = 1.0, pi2 = 0.0;  // rows A and (rp = 0) B
+  // pair product at frequency (row t, point j1), mirror at (row u, point j1m)
+  auto pair_q = [&](int t, int j1, int u, int j1m, bool pair, double &qr, double &qi) {
+    const A2 za = z[t * STR + pad32(j1)], zb = z[u * STR + pad32(j1m)];
+    const double ar = za.x, ai = za.y, br = zb.x, bi = -(double)zb.y;  // B = conj(Z[-j])
+    if (pair) {
+      const double dr = (ar * ar - ai * ai) - (br * br - bi * bi);
+      const double di = 2.0 * (ar * ai - br * bi);
+      qr = 0.25 * di;  // -i (A^2 - B^2) / 4
+      qi = -0.25 * dr;
+    } else {
+      qr = 0.5 * (ar + br);  // (A + B) / 2
+      qi = 0.5 * (ai + bi);
+    }
+  };
+  for (int q0 = p0; q0 < p1; q0 += KP) {
+    const int nk = min(KP, p1 - q0);
+    __syncthreads();  // the previous round's readers are done (and tw1 is written)
+    A2 v[NL];
+#pragma unroll
+    for (int g = 0; g < NL; ++g) {
+      const int i = min(tid + 256 * g, 2 * nk * N1 - 1);
+      const int t = i / N1, e = i % N1;  // transform t: pair q0 + t/2, row A or B
+      v[g] = cbuf[(s * n_pairs + q0 + t / 2) * (int64_t)M + (int64_t)((t & 1) ? rowB : rowA) * N1 + e];
+    }
+#pragma unroll
+    for (int g = 0; g < NL; ++g) {
+      const int i = tid + 256 * g;
+      if (i < 2 * nk * N1) z[(i / N1) * STR + pad32(bitrev<LOG2N1>(i % N1))] = v[g];
+    }
+    __syncthreads();
+    fft_lds_batch<A, LOG2N1, STR, 256>(z, tw1, 2 * nk);  // ends with a barrier
+    if (tid < N1) {
+      for (int k = 0; k < nk; ++k) {
+        const bool pair = pairs[2 * (q0 + k) + 1] >= 0;
+        double qr, qi, nr;
+        if (rp == 0) {
+          pair_q(2 * k, tid, 2 * k, (N1 - tid) & (N1 - 1), pair, qr, qi);  // row 0
+          nr = pr1 * qr - pi1 * qi;
+          pi1 = pr1 * qi + pi1 * qr;
+          pr1 = nr;
+          pair_q(2 * k + 1, tid, 2 * k + 1, N1 - 1 - tid, pair, qr, qi);  // row n2 / 2
+          nr = pr2 * qr - pi2 * qi;
+          pi2 = pr2 * qi + pi2 * qr;
+          pr2 = nr;
+        } else {
+          pair_q(2 * k, tid, 2 * k + 1, N1 - 1 - tid, pair, qr, qi);  // row j2, mirror in row n2 - j2
+          nr = pr1 * qr - pi1 * qi;
+          pi1 = pr1 * qi + pi1 * qr;
+          pr1 = nr;
+        }
       }
     }
-    if (tid < N1) acc += pr;
   }
-  const double tot = block_sum_256(acc, red);
-  if (tid == 0) partial[((int64_t)blockIdx.x * gridDim.y + s) * gridDim.z + blockIdx.z] = tot;
+  const double part = tid < N1 ? (rp == 0 ? pr1 + pr2 : 2.0 * pr1) : 0.0;
+  const double tot = block_sum_256(part, red);
+  if (tid == 0) partial[((int64_t)net * gridDim.y + s) * kBigRowPairs + rp] = tot;
 }
 
 __global__ __launch_bounds__(256) void m1_big_sum_kernel(const double *__restrict__ partial, int64_t n_nets,
@@ -390,29 +482,30 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const v
 }
 
 template <typename A>
-int combine_big(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const void *ybuf,
-                int64_t n_slots, int64_t n_tensors, int64_t samples, int64_t sample0, int64_t S, int log2m,
-                const void *tw, void *cbuf, double *partial, double *est, hipStream_t st) {
+int combine_big(int64_t n_nets, const int32_t *tslot, const int32_t *pairs, const int32_t *pair0,
+                int64_t n_pairs, const void *ybuf, int64_t n_slots, int64_t samples, int64_t sample0, int64_t S,
+                int log2m, const void *tw, void *cbuf, double *partial, double *est, hipStream_t st) {
   using A2 = typename Cplx<A>::type;
   const uint32_t m = 1u << log2m, n1 = m / kBigN2;
-  hipLaunchKernelGGL(m1_big_cols_kernel<A>, dim3((unsigned)n_tensors, (unsigned)samples, n1 / kBigCols), dim3(256), 0,
-                     st, tslot, reinterpret_cast<const A *>(ybuf), n_slots, n_tensors, log2m,
+  constexpr size_t lds = big_cols_lds<A>();
+  TN_HIP_CHECK(hipFuncSetAttribute((const void *)m1_big_cols_kernel<A>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(m1_big_cols_kernel<A>, dim3((unsigned)n_pairs, (unsigned)samples, n1 / big_cols<A>()),
+                     dim3(256), lds, st, tslot, pairs, n_pairs, reinterpret_cast<const A *>(ybuf), n_slots, log2m,
                      reinterpret_cast<const A2 *>(tw), reinterpret_cast<A2 *>(cbuf));
   TN_HIP_CHECK(hipGetLastError());
-  dim3 g2((unsigned)n_nets, (unsigned)samples, kBigN2 / kBigRows);
+  dim3 g2((unsigned)n_nets, (unsigned)samples, kBigRowPairs);
+  const A2 *cb = reinterpret_cast<const A2 *>(cbuf), *t2 = reinterpret_cast<const A2 *>(tw);
   if (log2m == 14)
-    hipLaunchKernelGGL((m1_big_rows_kernel<A, 6>), g2, dim3(256), 0, st, nets, reinterpret_cast<const A2 *>(cbuf),
-                       n_tensors, reinterpret_cast<const A2 *>(tw), partial);
+    hipLaunchKernelGGL((m1_big_rows_kernel<A, 6>), g2, dim3(256), 0, st, pair0, pairs, n_pairs, cb, t2, partial);
   else if (log2m == 15)
-    hipLaunchKernelGGL((m1_big_rows_kernel<A, 7>), g2, dim3(256), 0, st, nets, reinterpret_cast<const A2 *>(cbuf),
-                       n_tensors, reinterpret_cast<const A2 *>(tw), partial);
+    hipLaunchKernelGGL((m1_big_rows_kernel<A, 7>), g2, dim3(256), 0, st, pair0, pairs, n_pairs, cb, t2, partial);
   else
-    hipLaunchKernelGGL((m1_big_rows_kernel<A, 8>), g2, dim3(256), 0, st, nets, reinterpret_cast<const A2 *>(cbuf),
-                       n_tensors, reinterpret_cast<const A2 *>(tw), partial);
+    hipLaunchKernelGGL((m1_big_rows_kernel<A, 8>), g2, dim3(256), 0, st, pair0, pairs, n_pairs, cb, t2, partial);
   TN_HIP_CHECK(hipGetLastError());
-  const int64_t pairs = n_nets * samples;
-  hipLaunchKernelGGL(m1_big_sum_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, st, partial, n_nets,
-                     samples, kBigN2 / kBigRows, sample0, S, 1.0 / (double)m, est);
+  const int64_t np = n_nets * samples;
+  hipLaunchKernelGGL(m1_big_sum_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, partial, n_nets,
+                     samples, kBigRowPairs, sample0, S, 1.0 / (double)m, est);
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }
@@ -459,19 +552,21 @@ int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tslot,
                           st);
 }
 
-int launch_m1_combine_big(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, int dtype,
-                          const void *ybuf, int64_t n_slots, int64_t n_tensors, int64_t samples,
+int launch_m1_combine_big(int64_t n_nets, const int32_t *tslot, const int32_t *pairs, const int32_t *pair0,
+                          int64_t n_pairs, int dtype, const void *ybuf, int64_t n_slots, int64_t samples,
                           int64_t sample0, int64_t S, int log2m, const void *tw, void *cbuf, double *partial,
                           double *est, hipStream_t st) {
   if (n_nets == 0 || samples == 0) return TN_OK;
   if (samples > 65535) return set_error(TN_ERR_UNSUPPORTED, "combine: samples per launch");
   if (log2m < kMaxLog2Acc || log2m > kMaxLog2M1)
     return set_error(TN_ERR_ARG, "two-pass combine: m = 2^%d", log2m);
+  if (n_pairs > 0x7fffffff) return set_error(TN_ERR_UNSUPPORTED, "two-pass combine: %lld tensor pairs",
+                                             (long long)n_pairs);
   if (dtype == TN_F64)
-    return combine_big<double>(nets, n_nets, tslot, ybuf, n_slots, n_tensors, samples, sample0, S, log2m, tw,
-                               cbuf, partial, est, st);
-  return combine_big<float>(nets, n_nets, tslot, ybuf, n_slots, n_tensors, samples, sample0, S, log2m, tw, cbuf,
-                            partial, est, st);
+    return combine_big<double>(n_nets, tslot, pairs, pair0, n_pairs, ybuf, n_slots, samples, sample0, S, log2m,
+                               tw, cbuf, partial, est, st);
+  return combine_big<float>(n_nets, tslot, pairs, pair0, n_pairs, ybuf, n_slots, samples, sample0, S, log2m, tw,
+                            cbuf, partial, est, st);
 }
 
 int launch_m1_slots_to_tensors(const int32_t *tslot, int64_t n_tensors, int dtype,

@@ -393,6 +393,58 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
   }
 }
 
+// nb transforms of M points each, transform t at z + t * STR (STR >= pad32(M)),
+// element e of a transform at pad32(e); the same radix-2^2 passes as fft_lds,
+// with the groups of all transforms spread over the block (NTH threads) in
+// every pass.  tw is the padded half table of w_M.
+template <typename A, int LOG2M, int STR, int NTH>
+__device__ __forceinline__ void fft_lds_batch(typename Cplx<A>::type *z,
+                                              const typename Cplx<A>::type *__restrict__ tw, int nb) {
+  static_assert(LOG2M >= 2, "batched transforms of at least 4 points");
+  constexpr int M = 1 << LOG2M;
+  using A2 = typename Cplx<A>::type;
+  auto bfly = [](A2 &za, A2 &zb, const A2 w) {
+    const A tr = w.x * zb.x - w.y * zb.y;
+    const A ti = w.x * zb.y + w.y * zb.x;
+    zb = A2{za.x - tr, za.y - ti};
+    za = A2{za.x + tr, za.y + ti};
+  };
+  int lg = 1;
+  if constexpr ((LOG2M & 1) != 0) {
+    for (int q = threadIdx.x; q < nb * (M / 2); q += NTH) {
+      A2 *zt = z + (q >> (LOG2M - 1)) * STR;
+      const int qq = q & (M / 2 - 1);
+      A2 za = zt[pad32(2 * qq)], zb = zt[pad32(2 * qq + 1)];
+      bfly(za, zb, tw[0]);
+      zt[pad32(2 * qq)] = za;
+      zt[pad32(2 * qq + 1)] = zb;
+    }
+    __syncthreads();
+    lg = 2;
+  }
+#pragma unroll 1
+  for (; lg < LOG2M; lg += 2) {
+    const int h = 1 << (lg - 1);
+    for (int q = threadIdx.x; q < nb * (M / 4); q += NTH) {
+      A2 *zt = z + (q >> (LOG2M - 2)) * STR;
+      const int qq = q & (M / 4 - 1);
+      const int k = qq & (h - 1);
+      const int base = ((qq >> (lg - 1)) << (lg + 1)) + k;
+      A2 z0 = zt[pad32(base)], z1 = zt[pad32(base + h)], z2 = zt[pad32(base + 2 * h)], z3 = zt[pad32(base + 3 * h)];
+      const A2 w1 = tw[pad32(k << (LOG2M - lg))];
+      bfly(z0, z1, w1);
+      bfly(z2, z3, w1);
+      bfly(z0, z2, tw[pad32(k << (LOG2M - lg - 1))]);
+      bfly(z1, z3, tw[pad32((k + h) << (LOG2M - lg - 1))]);
+      zt[pad32(base)] = z0;
+      zt[pad32(base + h)] = z1;
+      zt[pad32(base + 2 * h)] = z2;
+      zt[pad32(base + 3 * h)] = z3;
+    }
+    __syncthreads();
+  }
+}
+
 template <int LOG2M>
 __device__ __forceinline__ int bitrev(int b) {
   if constexpr (LOG2M == 0) {

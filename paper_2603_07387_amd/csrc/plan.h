@@ -71,6 +71,9 @@ struct tn_plan {
   void *d_tw = nullptr;
   void *d_ybuf = nullptr;
   bool two_pass = false;        // the m-point FFT does not fit in LDS: two-pass combine
+  int64_t n_pairs = 0;          // its tensor pairs (two real sketches per complex transform)
+  int32_t *d_pairs = nullptr;   // [n_pairs][2]: tensors a, b (or -1)
+  int32_t *d_pair0 = nullptr;   // [n_nets + 1]: first pair of each network
   void *d_cbuf = nullptr;       // the two-pass combine's transposed columns
   double *d_partial = nullptr;  // and its per-block row sums
   int sb = 1;

@@ -196,7 +196,9 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: scatter needs %zu bytes of LDS", p->scatter_lds);
 
   const size_t per_sample = (size_t)p->W * 4 + p->h_slots.size() * (size_t)p->m * as +
-                            (p->two_pass ? (size_t)p->n_tensors * (size_t)p->m * 2 * as + (size_t)p->n_nets * 64 * 8 : 0);
+                            (p->two_pass ? (size_t)(p->n_tensors + p->n_nets) / 2 * (size_t)p->m * 2 * as +
+                                               (size_t)p->n_nets * kBigPartials * 8
+                                         : 0);
   int64_t chunk = (int64_t)std::max<size_t>(1, kWorkspaceBudget / std::max<size_t>(1, per_sample));
   chunk = std::min<int64_t>(chunk, p->S);
   chunk = std::min<int64_t>(chunk, 65535);
@@ -251,10 +253,23 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   if ((rc = dev_alloc(&yb, (size_t)chunk * p->h_slots.size() * (size_t)p->m * as)) != TN_OK) return rc;
   p->d_ybuf = yb;
   if (p->two_pass) {
+    // the tensors of each network two by two (an odd one out alone)
+    std::vector<int32_t> pairs, pair0;
+    for (const NetDesc &nd : p->h_nets) {
+      pair0.push_back((int32_t)(pairs.size() / 2));
+      for (int32_t k = nd.t0; k < nd.t1; k += 2) {
+        pairs.push_back(k);
+        pairs.push_back(k + 1 < nd.t1 ? k + 1 : -1);
+      }
+    }
+    pair0.push_back((int32_t)(pairs.size() / 2));
+    p->n_pairs = (int64_t)pairs.size() / 2;
+    if ((rc = upload(&p->d_pairs, pairs)) != TN_OK) return rc;
+    if ((rc = upload(&p->d_pair0, pair0)) != TN_OK) return rc;
     unsigned char *cb = nullptr;
-    if ((rc = dev_alloc(&cb, (size_t)chunk * (size_t)p->n_tensors * (size_t)p->m * 2 * as)) != TN_OK) return rc;
+    if ((rc = dev_alloc(&cb, (size_t)chunk * (size_t)p->n_pairs * (size_t)p->m * 2 * as)) != TN_OK) return rc;
     p->d_cbuf = cb;
-    if ((rc = dev_alloc(&p->d_partial, (size_t)chunk * (size_t)p->n_nets * 64)) != TN_OK) return rc;
+    if ((rc = dev_alloc(&p->d_partial, (size_t)chunk * (size_t)p->n_nets * kBigPartials)) != TN_OK) return rc;
   }
   if (p->m >= 2) {
     unsigned char *tw = nullptr;
@@ -346,8 +361,9 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
     if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
     if (p->two_pass)
-      rc = launch_m1_combine_big(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf, (int64_t)p->h_slots.size(),
-                                 p->n_tensors, n, c0, p->S, p->log2m, p->d_tw, p->d_cbuf, p->d_partial, est, st);
+      rc = launch_m1_combine_big(p->n_nets, p->d_tslot, p->d_pairs, p->d_pair0, p->n_pairs, p->dtype, p->d_ybuf,
+                                 (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, p->d_cbuf,
+                                 p->d_partial, est, st);
     else
       rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf, (int64_t)p->h_slots.size(), n,
                              c0, p->S, p->log2m, p->d_tw, est, st);
@@ -682,7 +698,8 @@ void plan_release(tn_plan *p) {
   if (p->m2) m2_release(p);
   void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data,    p->d_modes,
                   p->d_slots,   p->d_tslot,  p->d_nets,     p->d_tw,      p->d_ybuf,
-                  p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn, p->d_cbuf, p->d_partial};
+                  p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn, p->d_cbuf, p->d_partial,
+                  p->d_pairs,   p->d_pair0};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p->d_streams = nullptr;
@@ -694,6 +711,7 @@ void plan_release(tn_plan *p) {
   p->d_nets = nullptr;
   p->d_tw = p->d_ybuf = p->d_cbuf = nullptr;
   p->d_partial = nullptr;
+  p->d_pairs = p->d_pair0 = nullptr;
   p->d_est = nullptr;
   p->d_items = nullptr;
   p->d_counter = p->d_tensor_lgn = nullptr;

@@ -139,12 +139,15 @@ int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tensor
                       int dtype, const void *ybuf, int64_t n_slots, int64_t samples,
                       int64_t sample0, int64_t S, int log2m, const void *twiddles,
                       double *est, hipStream_t st);
-// m above 2^kMaxLog2Acc: the two-pass combine.  cbuf: samples x n_tensors x m
-// complex (A); partial: n_nets x samples x 64 doubles.
-int launch_m1_combine_big(const NetDesc *nets, int64_t n_nets, const int32_t *tensor_slot_begin, int dtype,
-                          const void *ybuf, int64_t n_slots, int64_t n_tensors, int64_t samples,
-                          int64_t sample0, int64_t S, int log2m, const void *tw, void *cbuf, double *partial,
-                          double *est, hipStream_t st);
+// The two-pass combine (the m-point FFT does not fit in LDS).  pairs: n_pairs x
+// (tensor a, tensor b or -1), the tensors of each network two by two; pair0:
+// n_nets + 1 offsets into pairs.  cbuf: samples x n_pairs x m complex (A);
+// partial: n_nets x samples x 128 doubles.
+int launch_m1_combine_big(int64_t n_nets, const int32_t *tensor_slot_begin, const int32_t *pairs,
+                          const int32_t *pair0, int64_t n_pairs, int dtype, const void *ybuf, int64_t n_slots,
+                          int64_t samples, int64_t sample0, int64_t S, int log2m, const void *tw, void *cbuf,
+                          double *partial, double *est, hipStream_t st);
+constexpr int kBigPartials = 128;  // partial sums per (network, sample) of the two-pass combine
 
 int launch_m1_slots_to_tensors(const int32_t *tensor_slot_begin, int64_t n_tensors, int dtype,
                                const void *ybuf, int64_t n_slots, int64_t samples, int log2m,
