@@ -78,6 +78,9 @@ __global__ __launch_bounds__(NT) void m1_scatter_kernel(
 
 // NTH threads: 256, or 1024 for m >= 8192 (a block then fills most of a
 // CU's LDS, and the per-thread share of the half spectrum stays small).
+// The transform is held padded in LDS (pad32).  TWL: the half table of
+// twiddles is staged beside it (padded too); otherwise (no room for it) the
+// two-level table (Tw2) is.
 template <typename A, int LOG2M, bool TWL, int NTH = 256>
 __global__ __launch_bounds__(NTH) void m1_combine_kernel(
     const NetDesc *__restrict__ nets, const int32_t *__restrict__ tslot,
@@ -98,14 +101,15 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
   const int64_t s = blockIdx.y;
   const A *y = ybuf + s * n_slots * (int64_t)M;
   const int tid = threadIdx.x;
-  // Twiddles: staged in LDS after z when the launch provides the room (every
-  // butterfly pass reads them; from the global table each pass would wait on
-  // a cache round trip).  With them, z and the twiddles are padded (pad32).
-  const A2 *twl = tw;
+  // Twiddles: staged in LDS after z (every butterfly pass reads them; from the
+  // global table each pass would wait on a cache round trip).  The first
+  // barrier below publishes them.
+  A2 *t = z + pad32(M);
   if constexpr (TWL) {
-    A2 *t = z + pad32(M);
     for (int j = tid; j < M / 2; j += NTH) t[pad32(j)] = tw[j];
-    twl = t;  // the first barrier below publishes it
+  } else {
+    static_assert(M >= 128, "two-level twiddles");
+    for (int j = tid; j < M / 128 + 64; j += NTH) t[j] = tw[j < M / 128 ? 64 * j : j - M / 128];
   }
 
   double pr[NC], pi[NC];
@@ -138,16 +142,19 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         const int b = b0 + g * NTH + tid;
-        if (b < M) z[TWL ? pad32(bitrev<LOG2M>(b)) : bitrev<LOG2M>(b)] = A2{v1[g], v2[g]};
+        if (b < M) z[pad32(bitrev<LOG2M>(b))] = A2{v1[g], v2[g]};
       }
     }
     __syncthreads();
-    fft_lds<A, LOG2M, TWL, NTH>(z, twl);
+    if constexpr (TWL)
+      fft_lds<A, LOG2M, true, NTH>(z, t);
+    else
+      fft_lds_tw<A, LOG2M, true, NTH>(z, Tw2<A>{t, t + M / 128});
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int j = tid + NTH * c;
       if (j < H) {
-        const A2 za = z[TWL ? pad32(j) : j], zb = z[TWL ? pad32((M - j) & (M - 1)) : (M - j) & (M - 1)];
+        const A2 za = z[pad32(j)], zb = z[pad32((M - j) & (M - 1))];
         const double ar = za.x, ai = za.y, br = zb.x, bi = -(double)zb.y;  // B = conj(Z[-j])
         double qr, qi;
         if (pair) {
@@ -463,22 +470,27 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const v
               int64_t n_slots, int64_t samples, int64_t sample0, int64_t S, const void *tw,
               double *est, hipStream_t st) {
   using A2 = typename Cplx<A>::type;
-  // z (m points) and, when the total stays within 64 KB, the m/2 twiddles, both
-  // with one spare element per 32 (bank spread)
-  constexpr size_t zt = sizeof(A2) * (size_t)((1 << LOG2M) + (1 << LOG2M) / 32 + (1 << LOG2M) / 2 + (1 << LOG2M) / 64 + 2);
-  constexpr bool TWL = LOG2M >= 1 && zt <= 65536;
-  constexpr int NTH = LOG2M >= 13 ? 1024 : 256;
-  auto kern = m1_combine_kernel<A, LOG2M, TWL, NTH>;
-  const size_t lds = TWL ? zt : sizeof(A2) << LOG2M;
-  if (lds > 65536)
-    TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds));
-  dim3 grid((unsigned)n_nets, (unsigned)samples);
-  hipLaunchKernelGGL(kern, grid, dim3(NTH), lds, st, nets, tslot,
-                     reinterpret_cast<const A *>(ybuf), n_slots, sample0, S,
-                     reinterpret_cast<const A2 *>(tw), est);
-  TN_HIP_CHECK(hipGetLastError());
-  return TN_OK;
+  // z (m points, one spare element per 32: bank spread) and, when the total
+  // stays within 64 KB, the m/2 twiddles (padded), else the two-level table
+  constexpr int M = 1 << LOG2M;
+  constexpr size_t zt = sizeof(A2) * (size_t)(M + M / 32 + M / 2 + M / 64 + 2);
+  constexpr bool TWL = zt <= 65536 || M < 128;
+  constexpr size_t lds = TWL ? zt : sizeof(A2) * (size_t)(M + M / 32 + M / 128 + 64);
+  if constexpr (lds > kMaxLdsBytes) {
+    return set_error(TN_ERR_UNSUPPORTED, "combine: the %d-point transform does not fit in LDS", M);
+  } else {
+    constexpr int NTH = LOG2M >= 13 ? 1024 : 256;
+    auto kern = m1_combine_kernel<A, LOG2M, TWL, NTH>;
+    if (lds > 65536)
+      TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds));
+    dim3 grid((unsigned)n_nets, (unsigned)samples);
+    hipLaunchKernelGGL(kern, grid, dim3(NTH), lds, st, nets, tslot,
+                       reinterpret_cast<const A *>(ybuf), n_slots, sample0, S,
+                       reinterpret_cast<const A2 *>(tw), est);
+    TN_HIP_CHECK(hipGetLastError());
+    return TN_OK;
+  }
 }
 
 template <typename A>

@@ -349,9 +349,9 @@ struct Cplx<double> {
 // bit-reversed loads and the twiddle reads over the LDS banks.
 __device__ __forceinline__ constexpr int pad32(int e) { return e + (e >> 5); }
 
-template <typename A, int LOG2M, bool PAD = false, int NTH = 256>
-__device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
-                                        const typename Cplx<A>::type *__restrict__ tw) {
+// twf(e) returns w_M^e for e < M/2.
+template <typename A, int LOG2M, bool PAD, int NTH, typename TwF>
+__device__ __forceinline__ void fft_lds_tw(typename Cplx<A>::type *z, TwF twf) {
   constexpr int M = 1 << LOG2M;
   using A2 = typename Cplx<A>::type;
   auto P = [](int e) { return PAD ? pad32(e) : e; };
@@ -363,9 +363,10 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
   };
   int lg = 1;
   if constexpr ((LOG2M & 1) != 0) {
+    const A2 w0 = twf(0);
     for (int q = threadIdx.x; q < M / 2; q += NTH) {
       A2 za = z[P(2 * q)], zb = z[P(2 * q + 1)];
-      bfly(za, zb, tw[0]);
+      bfly(za, zb, w0);
       z[P(2 * q)] = za;
       z[P(2 * q + 1)] = zb;
     }
@@ -379,11 +380,11 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
       const int k = q & (h - 1);
       const int base = ((q >> (lg - 1)) << (lg + 1)) + k;
       A2 z0 = z[P(base)], z1 = z[P(base + h)], z2 = z[P(base + 2 * h)], z3 = z[P(base + 3 * h)];
-      const A2 w1 = tw[P(k << (LOG2M - lg))];
+      const A2 w1 = twf(k << (LOG2M - lg));
       bfly(z0, z1, w1);  // stage lg: (base, base + h), (base + 2h, base + 3h)
       bfly(z2, z3, w1);
-      bfly(z0, z2, tw[P(k << (LOG2M - lg - 1))]);  // stage lg + 1: (base, base + 2h), (base + h, base + 3h)
-      bfly(z1, z3, tw[P((k + h) << (LOG2M - lg - 1))]);
+      bfly(z0, z2, twf(k << (LOG2M - lg - 1)));  // stage lg + 1: (base, base + 2h), (base + h, base + 3h)
+      bfly(z1, z3, twf((k + h) << (LOG2M - lg - 1)));
       z[P(base)] = z0;
       z[P(base + h)] = z1;
       z[P(base + 2 * h)] = z2;
@@ -392,6 +393,27 @@ __device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
     __syncthreads();
   }
 }
+
+// The twiddles from the half table tw[j] = w_M^j; TWPAD: the table is padded
+// the same way (it is, when staged in LDS).
+template <typename A, int LOG2M, bool PAD = false, int NTH = 256, bool TWPAD = PAD>
+__device__ __forceinline__ void fft_lds(typename Cplx<A>::type *z,
+                                        const typename Cplx<A>::type *__restrict__ tw) {
+  fft_lds_tw<A, LOG2M, PAD, NTH>(z, [tw](int e) { return tw[TWPAD ? pad32(e) : e]; });
+}
+
+// Two-level twiddles for transforms whose half table does not fit in LDS
+// beside them: w_M^e = hi[e / 64] lo[e % 64], hi[i] = w_M^(64 i) (M/128
+// entries), lo[j] = w_M^j (64 entries), one complex product per twiddle.
+template <typename A>
+struct Tw2 {
+  using A2 = typename Cplx<A>::type;
+  const A2 *hi, *lo;
+  __device__ __forceinline__ A2 operator()(int e) const {
+    const A2 a = hi[e >> 6], b = lo[e & 63];
+    return A2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+  }
+};
 
 // nb transforms of M points each, transform t at z + t * STR (STR >= pad32(M)),
 // element e of a transform at pad32(e); the same radix-2^2 passes as fft_lds,

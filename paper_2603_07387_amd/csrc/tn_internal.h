@@ -75,6 +75,7 @@ struct NetDesc {
 constexpr int kMaxCols = 1024;          // columns per slot (packed tables in LDS)
 constexpr int kMaxSlotEntries = 1 << 16;  // entries per scatter block
 constexpr int kMaxLog2M1 = 16;          // m <= 65536
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kMaxLog2Acc = 14;         // sketch words in LDS per scatter block and FFT points in LDS;
                                         // larger m: bucket ranges and the two-pass FFT
 
