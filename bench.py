@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--persistent", action="store_true",
                     help="cyclic method: the persistent fused kernel (TN_FLAG_PERSISTENT)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the unbatched comparison (one plan per network)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM byte counters)")
@@ -182,6 +184,29 @@ def m2_products(net, root=0):
     return out
 
 
+def plain_form(T, specs, meth, m, S, flags, steps, limit=256):
+    """The unbatched form on the same GPU: one plan per network (the first
+    `limit` networks of the workload), estimated one after another on the same
+    stream, same m, samples and flags.  Returns its estimates/s."""
+    import torch
+    specs = specs[:limit]
+    plans = [T.Plan([sp], meth, m, S, 0, flags=flags) for sp in specs]
+    stats = torch.empty(2, dtype=torch.float64, device="cuda")
+    for pl in plans:                       # warm-up (and the autotuner's runs)
+        pl.estimate(stats)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for pl in plans:
+            pl.estimate(stats)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for pl in plans:
+        pl.close()
+    return {"value": len(specs) * S * steps / wall, "unit": "estimates/s", "networks": len(specs),
+            "form": "one plan per network, estimated in turn on one stream"}
+
+
 def kernel_breakdown(T, specs, meth, m, S, flags, steps):
     """Device ms per step of each kernel kind, from a separate untimed pass of
     `steps` estimates with HIP events around every launch."""
@@ -249,6 +274,11 @@ def main():
     sk_ms, sk_n = plan.kernel_time(T.TN_KERNEL_SKETCH)
     avg_ms = sk_ms / max(1, sk_n)
     kt = kernel_breakdown(T, specs, meth, m, S, (flags & ~T.TN_FLAG_PROFILE_SKETCH), a.steps)
+    plain = None
+    if len(specs) > 1 and not a.no_plain:
+        plain = plain_form(T, specs, meth, m, S, flags & ~(T.TN_FLAG_PROFILE | T.TN_FLAG_PROFILE_SKETCH),
+                           min(a.steps, 5))
+        plain["batched_over_plain"] = value / plain["value"]
     entries = sum(n.nnz() for n in nets)
     esize = np.dtype(dtype).itemsize
     if method == "cyclic":
@@ -320,6 +350,7 @@ def main():
                     "median_samples_needed": float(np.median(need)),
                     "networks_per_s": float(len(nets) / np.sum(need) * value)},
         "kernel_ms_per_step": kt,
+        "plain": plain,
     }
     plan.close()
     if not a.no_cpu_baseline:
