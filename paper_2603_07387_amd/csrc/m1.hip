@@ -436,21 +436,29 @@ int scatter_sb(const M1Launch &L, hipStream_t st) {
   const bool ranged = L.log2m > kMaxLog2Acc;
   if (ranged && (SB != 1 || L.banks != 1))
     return set_error(TN_ERR_ARG, "scatter: m = 2^%d takes one bank and one sample per pass", L.log2m);
-  // One block per CU when its LDS exceeds half a CU's: then 1024 threads.
-  const bool wide = ranged || L.lds_bytes > kWideLds;
-  auto kern = ranged ? m1_scatter_kernel<T, A, SB, 1, true, 1024>
-              : wide ? (L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2, false, 1024>
-                                     : m1_scatter_kernel<T, A, SB, 1, false, 1024>)
+  if constexpr (SB * (16 / (int)sizeof(T)) > kMaxScatterWords) {
+    return set_error(TN_ERR_UNSUPPORTED, "scatter: %d samples per pass of %d-byte data", SB, (int)sizeof(T));
+  } else {
+    // One block per CU when its LDS exceeds half a CU's: then 1024 threads, or
+    // 512 where a thread's SB x (entries per 16-byte load) table words would
+    // not fit the 128 registers of a 1024-thread block.
+    constexpr int kWideNT = SB * (16 / (int)sizeof(T)) <= 16 ? 1024 : 512;
+    const bool wide = ranged || L.lds_bytes > kWideLds;
+    auto kern = wide ? (L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2, false, kWideNT>
+                                     : m1_scatter_kernel<T, A, SB, 1, false, kWideNT>)
                      : (L.banks == 2 ? m1_scatter_kernel<T, A, SB, 2> : m1_scatter_kernel<T, A, SB, 1>);
-  if (L.lds_bytes > 65536)
-    TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)L.lds_bytes));
-  dim3 grid((unsigned)L.n_slots, (unsigned)((L.samples + SB - 1) / SB),
-            ranged ? 1u << (L.log2m - kMaxLog2Acc) : 1u);
-  hipLaunchKernelGGL(kern, grid, dim3(wide ? 1024 : 256 * L.banks), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
-                     L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, reinterpret_cast<A *>(L.ybuf));
-  TN_HIP_CHECK(hipGetLastError());
-  return TN_OK;
+    if constexpr (SB == 1)
+      if (ranged) kern = m1_scatter_kernel<T, A, 1, 1, true, 1024>;
+    if (L.lds_bytes > 65536)
+      TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)L.lds_bytes));
+    dim3 grid((unsigned)L.n_slots, (unsigned)((L.samples + SB - 1) / SB),
+              ranged ? 1u << (L.log2m - kMaxLog2Acc) : 1u);
+    hipLaunchKernelGGL(kern, grid, dim3(ranged ? 1024 : wide ? kWideNT : 256 * L.banks), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
+                       L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, reinterpret_cast<A *>(L.ybuf));
+    TN_HIP_CHECK(hipGetLastError());
+    return TN_OK;
+  }
 }
 
 template <typename T, typename A>

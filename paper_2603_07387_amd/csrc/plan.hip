@@ -188,7 +188,9 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   }
   if (const char *env = getenv("TN_SCATTER_SB"); env && !big) {
     const int sb = atoi(env);
-    if ((sb == 1 || sb == 2 || sb == 4 || sb == 8 || sb == 16) && lds_for(sb) <= p->max_lds) p->sb = sb;
+    if ((sb == 1 || sb == 2 || sb == 4 || sb == 8 || sb == 16) && lds_for(sb) <= p->max_lds &&
+        scatter_words(sb, p->dtype) <= kMaxScatterWords)
+      p->sb = sb;
   }
   p->scatter_lds = lds_for(p->sb);
   p->worst_cols_rows = worst_cols_rows;
@@ -426,7 +428,7 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
         p->banks = banks;
         const size_t lds = scatter_lds_for(p, sb);
         p->banks = save;
-        if (lds > p->max_lds) break;
+        if (lds > p->max_lds || scatter_words(sb, p->dtype) > kMaxScatterWords) break;
       }
       for (int rep = 0; rep < 2 && rc == TN_OK; ++rep) {
         if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");

@@ -76,6 +76,11 @@ constexpr int kMaxCols = 1024;          // columns per slot (packed tables in LD
 constexpr int kMaxSlotEntries = 1 << 16;  // entries per scatter block
 constexpr int kMaxLog2M1 = 16;          // m <= 65536
 constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+// Column-table words a scatter thread holds per load: samples per pass x
+// entries per 16-byte load.  Above 64 the scatter would spill registers, so
+// such schedules are not offered.
+constexpr int kMaxScatterWords = 64;
+inline int scatter_words(int sb, int dtype) { return sb * (dtype == TN_F64 ? 2 : dtype == TN_F32 ? 4 : 8); }
 constexpr int kMaxLog2Acc = 14;         // sketch words in LDS per scatter block and FFT points in LDS;
                                         // larger m: bucket ranges and the two-pass FFT
 

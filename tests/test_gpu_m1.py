@@ -147,6 +147,18 @@ def test_torus_large_m(T, orc, m, dtype):
     check_estimates(orc, plan, views, 5, dtype)
 
 
+@pytest.mark.parametrize("m", [8192, 16384, 32768, 65536])
+def test_large_m_odd_networks_fp32(T, orc, m):
+    """FP32 sketches at large m with odd tensor counts (a tensor alone in its
+    complex transform): the in-LDS combine with two-level twiddles and 1024
+    threads (m = 8192, 16384) and the two-pass combine with tensor pairs and
+    mirror-row blocks (m = 32768, 65536), against the oracle per sample."""
+    nets = [W.triangle(24, seed=7), W.ring(5, 10, seed=8), W.random_network(7, 6)]
+    plan, views = make_plan(T, nets, "float32", m, 3, 31)
+    assert plan.query(8) == 1 or m <= 16384
+    check_estimates(orc, plan, views, 31, "float32")
+
+
 def test_large_m_multi_slot_and_sketches(T, orc):
     """m = 65536 with a tensor split into several slots, a triangle and a ring in
     one plan; the exported sketches match the oracle's bucket by bucket.  (The
