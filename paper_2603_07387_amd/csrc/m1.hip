@@ -227,9 +227,12 @@ __device__ __forceinline__ A2 twiddle_at(const A2 *__restrict__ tw, uint32_t e, 
 // for FP32 sketches, 256 bytes for FP64 (the transforms then fill 68 KB of LDS).
 template <typename A>
 constexpr int big_cols() { return sizeof(A) == 4 ? 32 : 16; }
+// LDS: the batch of transforms, the padded 256-point half table, and the
+// two-level table of the transposed store's twiddles w_m^e = hi[e / 256]
+// lo[e % 256] (m / 256 <= 256 and 256 entries).
 template <typename A>
 constexpr size_t big_cols_lds() {
-  return sizeof(typename Cplx<A>::type) * (size_t)(big_cols<A>() * kBigStr + kBigN2 / 2 + kBigN2 / 64);
+  return sizeof(typename Cplx<A>::type) * (size_t)(big_cols<A>() * kBigStr + kBigN2 / 2 + kBigN2 / 64 + 2 * kBigN2);
 }
 
 template <typename A>
@@ -247,11 +250,14 @@ __global__ __launch_bounds__(256) void m1_big_cols_kernel(const int32_t *__restr
   extern __shared__ __align__(16) unsigned char smem[];
   A2 *z = reinterpret_cast<A2 *>(smem);
   A2 *tw2 = z + CB * kBigStr;
+  A2 *thi = tw2 + kBigN2 / 2 + kBigN2 / 64, *tlo = thi + kBigN2;
   const uint32_t m = 1u << log2m, n1 = m / kBigN2;
   const int64_t pr = blockIdx.x, s = blockIdx.y;
   const uint32_t b1_0 = blockIdx.z * CB;
   const int tid = threadIdx.x, c = tid % CB, r0 = tid / CB;
   if (tid < kBigN2 / 2) tw2[pad32(tid)] = tw[(uint32_t)tid * n1];  // w_n2^t = w_m^(t n1)
+  if ((uint32_t)tid < n1) thi[tid] = twiddle_at(tw, (uint32_t)tid * kBigN2, m);  // (published by the
+  tlo[tid] = twiddle_at(tw, (uint32_t)tid, m);                                  //  barrier below)
   const int ta = pairs[2 * pr], tb = pairs[2 * pr + 1];
   const int a0 = tslot[ta], a1 = tslot[ta + 1];
   const int bb0 = tb >= 0 ? tslot[tb] : 0, bb1 = tb >= 0 ? tslot[tb + 1] : 0;
@@ -282,7 +288,9 @@ __global__ __launch_bounds__(256) void m1_big_cols_kernel(const int32_t *__restr
 #pragma unroll 4
   for (int i = 0; i < RPT; ++i) {
     const int j2 = r0 + RS * i;
-    const A2 v = z[c * kBigStr + pad32(j2)], w = twiddle_at(tw, b1 * (uint32_t)j2, m);
+    const uint32_t e = (b1 * (uint32_t)j2) & (m - 1);
+    const A2 v = z[c * kBigStr + pad32(j2)], wh = thi[e / kBigN2], wl = tlo[e % kBigN2];
+    const A2 w = A2{wh.x * wl.x - wh.y * wl.y, wh.x * wl.y + wh.y * wl.x};
     out[(int64_t)j2 * n1] = A2{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
   }
 }
