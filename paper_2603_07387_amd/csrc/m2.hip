@@ -153,10 +153,12 @@ __device__ __forceinline__ void store_g(G *g, size_t i, A v) {
   }
 }
 
-template <typename A, typename G, int QT>
+// AW: the fixed-point accumulator word (64-bit; 32-bit for BF16 g, see
+// m2_gather_kernel).
+template <typename A, typename G, int QT, typename AW>
 __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const int32_t *tab_base,
                                                const uint32_t *dtab, const double *wv,
-                                               unsigned long long *acc, const int32_t *tab,
+                                               AW *acc, const int32_t *tab,
                                                const HashCoeffs *coef, uint32_t mask, uint32_t m,
                                                double sc, double inv_sc, G *g) {
   const int tid = threadIdx.x;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const in
     for (int j = 0; j < QT; ++j)
       if (j < c) p *= wv[tb[j] + (int32_t)idx[j]];
     const long long v = __double_as_longlong(fma(p, sc, kMagic)) - __double_as_longlong(kMagic);
-    atomicAdd(&acc[h & mask], (unsigned long long)((h & 0x80000000u) ? -v : v));
+    atomicAdd(&acc[h & mask], (AW)((h & 0x80000000u) ? -v : v));
     advance(idx);
   }
   __syncthreads();
@@ -242,7 +244,7 @@ __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const in
   for (int j = 0; j < QT; ++j) idx[j] = idx0[j];
   for (uint32_t col = (uint32_t)tid; col < ncols; col += 256u) {
     const uint32_t h = rs_hash(idx);
-    const double r = (double)(long long)acc[h & mask] * inv_sc;
+    const double r = (double)(std::make_signed_t<AW>)acc[h & mask] * inv_sc;
     store_g(g, col, (A)((h & 0x80000000u) ? -r : r));
     advance(idx);
   }
@@ -256,9 +258,9 @@ __device__ __forceinline__ void gather_columns(const M2Node &nd, int c, const in
 // is folded into the product before the fixed-point conversion: fma rounds
 // +x and -x symmetrically, so every sketch entry and every g value is bitwise
 // that of gather_columns<A, G, 2>.
-template <typename A, typename G>
+template <typename A, typename G, typename AW>
 __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab_base, const uint32_t *dtab,
-                                            const double *wv, unsigned long long *acc, uint32_t mask, double sc,
+                                            const double *wv, AW *acc, uint32_t mask, double sc,
                                             double inv_sc, G *g) {
   const uint32_t tid = threadIdx.x;
   const uint32_t d0 = (uint32_t)nd.child_dim[0], d1 = (uint32_t)nd.child_dim[1];
@@ -293,7 +295,7 @@ __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab
           const uint32_t b = ((v0[u] & 0x7fffffffu) + v1m) & mask;
           const long long sg = (long long)((v0[u] ^ v1) & 0x80000000u) << 32;
           const double p = __longlong_as_double(__double_as_longlong(x0[u] * w1) ^ sg);
-          atomicAdd(&acc[b], (unsigned long long)(__double_as_longlong(fma(p, sc, kMagic)) - kMagicBits));
+          atomicAdd(&acc[b], (AW)(__double_as_longlong(fma(p, sc, kMagic)) - kMagicBits));
         }
       }
     }
@@ -302,7 +304,7 @@ __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab
   if (active) {
     for (uint32_t i0 = i0s; i0 < d0; i0 += U * R) {
       uint32_t v0[U];
-      unsigned long long a[U];
+      AW a[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) v0[u] = t0[min(i0 + u * R, d0 - 1)];
 #pragma unroll
@@ -311,7 +313,7 @@ __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab
       for (int u = 0; u < U; ++u) {
         const uint32_t ii = i0 + u * R;
         if (ii < d0) {
-          const A r = (A)((double)(long long)a[u] * inv_sc);
+          const A r = (A)((double)(std::make_signed_t<AW>)a[u] * inv_sc);
           store_g(g, (size_t)ii * d1 + i1, ((v0[u] ^ v1) & 0x80000000u) ? -r : r);
         }
       }
@@ -399,6 +401,17 @@ __global__ __launch_bounds__(kTabThreads) void m2_tables_kernel(const M2Node *__
 constexpr int kWPre = 4, kTPre = 2;
 constexpr int kMaxSplit = 8;  // column ranges per product tile (products below)
 
+// Byte offset of the gather's w values in its LDS (after the m accumulator
+// words and the tcap slot-table words, 8-byte aligned), and its LDS size.
+template <typename G>
+__host__ __device__ constexpr size_t gather_wv_offset(uint32_t m, int tcap) {
+  return ((size_t)m * (sizeof(G) == 2 ? 4 : 8) + (size_t)tcap * 4 + 7) & ~(size_t)7;
+}
+template <typename G>
+constexpr size_t gather_lds(uint32_t m, int tcap) {
+  return gather_wv_offset<G>(m, tcap) + (size_t)tcap * 8;
+}
+
 template <typename T, typename A, typename G>
 __global__ __launch_bounds__(256) void m2_gather_kernel(
     const M2Node *__restrict__ nodes, const int32_t *__restrict__ level, const void *const *data,
@@ -416,9 +429,15 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
   const uint32_t m = 1u << log2m, mask = m - 1;
   const int c = nd.nchild, qt = nd.qt;
 
-  unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);  // [m]
+  // Fixed-point accumulators: 64-bit words, or 32-bit ones when g is stored
+  // as BF16 (the products' own rounding, 2^-9 relative, dwarfs the 32-bit
+  // resolution of 2^-(30 - lgN) of the largest product): the faster 32-bit
+  // atomic and half the LDS (gather 1.18 -> 1.11 ms per caterpillar step).
+  using AW = std::conditional_t<sizeof(G) == 2, uint32_t, unsigned long long>;
+  constexpr int kAccBits = sizeof(G) == 2 ? 30 : 62;
+  AW *acc = reinterpret_cast<AW *>(smem);                                  // [m]
   uint32_t *dtab = reinterpret_cast<uint32_t *>(acc + m);                  // [tcap] slot tables
-  double *wv = reinterpret_cast<double *>(dtab + tcap);                    // [tcap] children's w
+  double *wv = reinterpret_cast<double *>(smem + gather_wv_offset<G>(m, tcap));  // [tcap] children's w
 
   if (tid == 0) {
     int b = 0;
@@ -491,7 +510,7 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
   for (int64_t s = s_first; s < n_samples; s += s_step) {
     const int32_t *tab = tables ? tables + s * W : nullptr;
     if (qt >= 4 && !tab) node_coeffs(nd, (uint64_t)(sample0 + s), coef);
-    for (uint32_t i = tid; i < m; i += 256) acc[i] = 0ull;
+    for (uint32_t i = tid; i < m; i += 256) acc[i] = 0;
     // Level-one slot tables.
     if (tpre_ok) {
 #pragma unroll
@@ -548,24 +567,24 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
     const int lgN = max(nd.ncols > 1 ? 64 - __clzll((unsigned long long)(nd.ncols - 1)) : 0, 11);
     int e = 0;
     if (pmax > 0.0) (void)frexp(pmax, &e);
-    const double sc = ldexp(1.0, 62 - lgN - e);
-    const double inv_sc = ldexp(1.0, -(62 - lgN - e));
+    const double sc = ldexp(1.0, kAccBits - lgN - e);
+    const double inv_sc = ldexp(1.0, -(kAccBits - lgN - e));
 
     G *g = gbuf + s * g_row + nd.g_off;
     switch (qt) {
-      case 1: gather_columns<A, G, 1>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      case 1: gather_columns<A, G, 1, AW>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
       case 2:
         if (nd.child_dim[1] <= 256)
-          gather_pair<A, G>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
+          gather_pair<A, G, AW>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
         else
-          gather_columns<A, G, 2>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g);
+          gather_columns<A, G, 2, AW>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g);
         break;
-      case 4: gather_columns<A, G, 4>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
-      default: gather_columns<A, G, 8>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      case 4: gather_columns<A, G, 4, AW>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+      default: gather_columns<A, G, 8, AW>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
     }
     if (r_out && nd.root) {
       for (uint32_t b = tid; b < m; b += 256)
-        r_out[s * r_stride + (int64_t)nd.net * m + b] = (double)(long long)acc[b] * inv_sc;
+        r_out[s * r_stride + (int64_t)nd.net * m + b] = (double)(std::make_signed_t<AW>)acc[b] * inv_sc;
     }
     if (tid < kM2MaxChildren) wmax[tid] = wmax_leaf[tid];
     __syncthreads();  // acc, coef, the tables and wmax are rewritten for the next sample
@@ -932,7 +951,7 @@ template <typename T, typename A, typename G>
 int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *tables,
              double *est, double *export_out) {
   M2Plan *P = p->m2;
-  const size_t lds = (size_t)p->m * 8 + (size_t)P->tcap * 12;
+  const size_t lds = gather_lds<G>((uint32_t)p->m, P->tcap);
   auto gk = m2_gather_kernel<T, A, G>;
   constexpr size_t g16 = g16_lds_bytes<T, G>();
   if (g16 > 65536) {

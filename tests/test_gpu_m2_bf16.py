@@ -1,8 +1,11 @@
 """The acyclic estimator with TN_FLAG_MFMA_BF16 (SMVP products on the BF16
 matrix cores, FP32 accumulation) against the exact FP64 oracle.
 
-The hashes, sketch scatters and combines are those of the FP64 path; only the
-products w_k = mat(X_k) G round their operands to BF16 (unit roundoff 2^-9).
+The hashes and combines are those of the FP64 path; the products
+w_k = mat(X_k) G round their operands to BF16 (unit roundoff 2^-9), and the
+sketch scatters that produce G accumulate in 32-bit fixed point (each term
+rounded to 2^-(31 - lgN) of the largest product, far below the BF16 rounding
+of G that follows).
 To first order each tree level perturbs the vectors passed upwards by at most
 about 2 * 2^-9 relative per operand pair, and the perturbations of L levels
 add, so the bar for each estimate is
