@@ -412,7 +412,9 @@ constexpr size_t gather_lds(uint32_t m, int tcap) {
   return gather_wv_offset<G>(m, tcap) + (size_t)tcap * 8;
 }
 
-template <typename T, typename A, typename G>
+// PAIR: every node of the launch has two children, the second of at most 256
+// values (the two-child loop only: fewer registers, more blocks per CU).
+template <typename T, typename A, typename G, bool PAIR = false>
 __global__ __launch_bounds__(256) void m2_gather_kernel(
     const M2Node *__restrict__ nodes, const int32_t *__restrict__ level, const void *const *data,
     const int32_t *__restrict__ tables, int64_t W, int64_t sample0, int64_t n_samples, int log2m,
@@ -571,6 +573,9 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
     const double inv_sc = ldexp(1.0, -(kAccBits - lgN - e));
 
     G *g = gbuf + s * g_row + nd.g_off;
+    if constexpr (PAIR) {
+      gather_pair<A, G, AW>(nd, tab_base, dtab, wv, acc, mask, sc, inv_sc, g);
+    } else {
     switch (qt) {
       case 1: gather_columns<A, G, 1, AW>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
       case 2:
@@ -581,6 +586,7 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
         break;
       case 4: gather_columns<A, G, 4, AW>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
       default: gather_columns<A, G, 8, AW>(nd, c, tab_base, dtab, wv, acc, tab, coef, mask, m, sc, inv_sc, g); break;
+    }
     }
     if (r_out && nd.root) {
       for (uint32_t b = tid; b < m; b += 256)
@@ -953,6 +959,7 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
   M2Plan *P = p->m2;
   const size_t lds = gather_lds<G>((uint32_t)p->m, P->tcap);
   auto gk = m2_gather_kernel<T, A, G>;
+  auto gkp = m2_gather_kernel<T, A, G, true>;
   constexpr size_t g16 = g16_lds_bytes<T, G>();
   if (g16 > 65536) {
     if constexpr (sizeof(G) == sizeof(A))
@@ -961,9 +968,12 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
   }
-  if (lds > 65536)
+  if (lds > 65536) {
     TN_HIP_CHECK(hipFuncSetAttribute((const void *)gk, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
+    TN_HIP_CHECK(hipFuncSetAttribute((const void *)gkp, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+  }
   if (!P->all_nodes.empty()) {
     hipEvent_t ev = nullptr;
     int rc;
@@ -980,11 +990,20 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_COMBINE)) != TN_OK) return rc;
     // the children's depth left its products as column partials: summed here
     const bool cfuse = !export_out && (size_t)d + 1 < P->level_fuse.size() && P->level_fuse[(size_t)d + 1];
-    // Samples per block: about 1024 blocks per level (four resident per CU).
+    // Every node of the depth with two children, the second of at most 256
+    // values: the two-child kernel (74-80 registers against 116-123).
+    bool pair = true;
+    for (int32_t i : P->level_nodes[(size_t)d]) {
+      const M2Node &nd = P->h_nodes[(size_t)i];
+      pair = pair && nd.nchild == 2 && nd.child_dim[1] <= 256;
+    }
+    // Samples per block: about 1024 blocks per level (four resident per CU;
+    // six for the two-child kernel with BF16 g's 32-bit sketches).
     const int64_t nn = (int64_t)P->level_nodes[(size_t)d].size();
-    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, (1024 + nn - 1) / nn));
+    const int64_t target = pair && sizeof(G) == 2 ? 1536 : 1024;
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, (target + nn - 1) / nn));
     dim3 g1((unsigned)nn, (unsigned)gy);
-    hipLaunchKernelGGL(gk, g1, dim3(256), lds, st, P->d_nodes, P->d_level_nodes[(size_t)d],
+    hipLaunchKernelGGL(pair ? gkp : gk, g1, dim3(256), lds, st, P->d_nodes, P->d_level_nodes[(size_t)d],
                        (const void *const *)p->d_data, tables, p->W, c0, n, p->log2m, P->d_ltab, P->level_off[(size_t)d],
                        reinterpret_cast<const A *>(P->d_w), P->w_row,
                        reinterpret_cast<G *>(P->d_g), P->g_row,
