@@ -236,7 +236,9 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       load_cols<VEC>(colt + s * L + c, lv[s]);
     }
   };
-  constexpr int UNROLL = 4;                  // 16-byte loads in flight per thread
+  // 16-byte loads in flight per thread: 8 in the 512-thread blocks (two per CU,
+  // registers to spare; half the barriers per entry), else 4
+  constexpr int UNROLL = NT == 512 && SB * VEC <= 16 ? 8 : 4;
   const bool vec = (L % VEC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
   if (vec) {
     // Rows are multiples of VEC long and the slot starts 16-byte aligned, so
