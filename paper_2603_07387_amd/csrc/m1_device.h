@@ -3,6 +3,8 @@
 // slot scatter and the LDS FFT.
 #pragma once
 
+#include <type_traits>
+
 #include "tn_internal.h"
 
 namespace tn {
@@ -254,54 +256,132 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
     // load latency hides behind the LDS atomics; small blocks overlap with
     // other blocks instead and keep the registers.
     constexpr bool PREFETCH = NT >= 512;
-    V buf[UNROLL], nxt[UNROLL];
-    if constexpr (PREFETCH) {
+    if constexpr (NT == 512) {
+      // 512-thread blocks: when NT * VEC is a multiple of the row length, every
+      // vector a thread loads starts at the same column (tid * VEC) mod L, so
+      // its column-table entries are read once, not once per vector (a third
+      // of the loop's LDS bytes otherwise).  The loop is instantiated for both
+      // cases; blocks of other sizes keep the general loop below (they have no
+      // registers to spare for a second instantiation).
+      auto vec_loop = [&](auto FIXED_) {
+        constexpr bool FIXED = decltype(FIXED_)::value;
+        uint32_t lvf[SB][VEC];
+        if constexpr (FIXED) {
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
-    }
-    for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
+          for (int s = 0; s < SB; ++s) load_cols<VEC>(colt + s * L + ((uint32_t)tid * VEC) % (uint32_t)L, lvf[s]);
+        }
+        V buf[UNROLL], nxt[UNROLL];
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
-      double lmax = 0.0;
+        for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
+        for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const T *xs = reinterpret_cast<const T *>(&buf[u]);
+          for (int u = 0; u < UNROLL; ++u) buf[u] = nxt[u];
+          double lmax = 0.0;
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
-      }
-      update_scale(lmax);
-      if (PREFETCH && v0 + NT * UNROLL < NV) {  // uniform over the block
+          for (int u = 0; u < UNROLL; ++u) {
+            const T *xs = reinterpret_cast<const T *>(&buf[u]);
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
-      }
-      uint32_t rr[UNROLL], cc[UNROLL];
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const uint32_t e = min(v0 + u * NT + tid, NV - 1) * VEC;  // clamped: valid table reads
-        rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
-        cc[u] = e - rr[u] * (uint32_t)L;
-      }
-      // Software pipeline: the table reads of vector u + 1 are issued before the
-      // adds of vector u.
-      uint32_t hv[2][SB], lv[2][SB][VEC];
-      read_tabs(rr[0], cc[0], hv[0], lv[0]);
-#pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
-        if (v0 + u * NT + tid < NV) {
-          const T *xs = reinterpret_cast<const T *>(&buf[u]);
-          long long q[VEC], nq[VEC];
-#pragma unroll
-          for (int i = 0; i < VEC; ++i) {
-            q[i] = to_fixed((double)to_acc_any(xs[i]));
-            nq[i] = BANKS == 2 ? 0 : -q[i];
+            for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
           }
+          update_scale(lmax);
+          if (v0 + NT * UNROLL < NV) {  // uniform over the block
 #pragma unroll
-          for (int s = 0; s < SB; ++s)
-            if (s < nsb) {
+            for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
+          }
+          uint32_t rr[UNROLL], cc[UNROLL];
 #pragma unroll
-              for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i], nq[i]);
+          for (int u = 0; u < UNROLL; ++u) {
+            const uint32_t e = min(v0 + u * NT + tid, NV - 1) * VEC;  // clamped: valid table reads
+            rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
+            cc[u] = e - rr[u] * (uint32_t)L;
+          }
+          // the table reads of vector u + 1 are issued before the adds of vector u
+          uint32_t hv[2][SB], lv[2][SB][VEC];
+          auto tabs = [&](int u, int k) {
+            if constexpr (FIXED) {
+#pragma unroll
+              for (int s = 0; s < SB; ++s) hv[k][s] = rowt[s * rows + rr[u]];
+            } else {
+              read_tabs(rr[u], cc[u], hv[k], lv[k]);
             }
+          };
+          tabs(0, 0);
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            if (u + 1 < UNROLL) tabs(u + 1, (u + 1) & 1);
+            if (v0 + u * NT + tid < NV) {
+              const T *xs = reinterpret_cast<const T *>(&buf[u]);
+              long long q[VEC], nq[VEC];
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) {
+                q[i] = to_fixed((double)to_acc_any(xs[i]));
+                nq[i] = BANKS == 2 ? 0 : -q[i];
+              }
+#pragma unroll
+              for (int s = 0; s < SB; ++s)
+                if (s < nsb) {
+#pragma unroll
+                  for (int i = 0; i < VEC; ++i)
+                    add_fixed(s, hv[u & 1][s], FIXED ? lvf[s][i] : lv[u & 1][s][i], q[i], nq[i]);
+                }
+            }
+          }
+        }
+      };
+      if (((uint32_t)(NT * VEC)) % (uint32_t)L == 0)
+        vec_loop(std::true_type{});
+      else
+        vec_loop(std::false_type{});
+    } else {
+          V buf[UNROLL], nxt[UNROLL];
+      if constexpr (PREFETCH) {
+  #pragma unroll
+        for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
+      }
+      for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
+  #pragma unroll
+        for (int u = 0; u < UNROLL; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
+        double lmax = 0.0;
+  #pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const T *xs = reinterpret_cast<const T *>(&buf[u]);
+  #pragma unroll
+          for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+        }
+        update_scale(lmax);
+        if (PREFETCH && v0 + NT * UNROLL < NV) {  // uniform over the block
+  #pragma unroll
+          for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
+        }
+        uint32_t rr[UNROLL], cc[UNROLL];
+  #pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const uint32_t e = min(v0 + u * NT + tid, NV - 1) * VEC;  // clamped: valid table reads
+          rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
+          cc[u] = e - rr[u] * (uint32_t)L;
+        }
+        // Software pipeline: the table reads of vector u + 1 are issued before the
+        // adds of vector u.
+        uint32_t hv[2][SB], lv[2][SB][VEC];
+        read_tabs(rr[0], cc[0], hv[0], lv[0]);
+  #pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
+          if (v0 + u * NT + tid < NV) {
+            const T *xs = reinterpret_cast<const T *>(&buf[u]);
+            long long q[VEC], nq[VEC];
+  #pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+              q[i] = to_fixed((double)to_acc_any(xs[i]));
+              nq[i] = BANKS == 2 ? 0 : -q[i];
+            }
+  #pragma unroll
+            for (int s = 0; s < SB; ++s)
+              if (s < nsb) {
+  #pragma unroll
+                for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i], nq[i]);
+              }
+          }
         }
       }
     }
