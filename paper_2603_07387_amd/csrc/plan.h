@@ -50,6 +50,7 @@ struct tn_plan {
 
   // hash streams
   std::vector<tn::StreamDesc> h_streams;
+  int64_t max_stream = 0;  // the longest stream's indices
   int64_t W = 0;
   tn::StreamDesc *d_streams = nullptr;
   int32_t *d_tables = nullptr;    // [chunk][W]

@@ -292,7 +292,7 @@ int m1_tables(tn_plan *p, int64_t c0, int64_t n, hipStream_t st, const int32_t *
   hipEvent_t ev = nullptr;
   int rc = prof_begin(p, st, &ev, TN_KERNEL_HASH);
   if (rc == TN_OK)
-    rc = launch_hashgen(p->d_streams, (int64_t)p->h_streams.size(), p->W, c0, n, p->m,
+    rc = launch_hashgen(p->d_streams, (int64_t)p->h_streams.size(), p->W, c0, n, p->m, p->max_stream,
                         p->d_tables, st);
   if (rc == TN_OK) rc = prof_end(p, st, TN_KERNEL_HASH, ev);
   return rc;
@@ -603,6 +603,8 @@ int plan_build(tn_plan *p, const tn_network *nets, int n_nets, int method, int64
     plan_release(p);
     return rc;
   }
+  p->max_stream = 0;
+  for (const StreamDesc &sd : p->h_streams) p->max_stream = std::max<int64_t>(p->max_stream, (int64_t)sd.n);
   if ((rc = dev_alloc(&p->d_est, (size_t)n_nets * (size_t)S)) != TN_OK) { plan_release(p); return rc; }
   if ((rc = dev_alloc(&p->d_data, (size_t)p->n_tensors)) != TN_OK) { plan_release(p); return rc; }
   p->bound.assign((size_t)p->n_tensors, nullptr);
@@ -750,7 +752,7 @@ int plan_get_hashes(tn_plan *p, int64_t first, int64_t count, hipStream_t st, in
   for (int64_t c = 0; c < count; c += 65535) {
     const int64_t n = std::min<int64_t>(65535, count - c);
     int rc = launch_hashgen(p->d_streams, (int64_t)p->h_streams.size(), p->W, first + c, n, p->m,
-                            out + c * p->W, st);
+                            p->max_stream, out + c * p->W, st);
     if (rc != TN_OK) return rc;
   }
   return TN_OK;

@@ -136,8 +136,9 @@ struct M1FusedLaunch {
 size_t m1_fused_lds(int sb, int banks, int64_t m, int32_t worst);
 int launch_m1_fused(const M1FusedLaunch &L, hipStream_t st);
 
+// max_n: the longest stream (indices); all at most 64 take one thread per (stream, sample).
 int launch_hashgen(const StreamDesc *streams, int64_t n_streams, int64_t W, int64_t sample0,
-                   int64_t samples, int64_t m, int32_t *out, hipStream_t st);
+                   int64_t samples, int64_t m, int64_t max_n, int32_t *out, hipStream_t st);
 
 int launch_m1_scatter(const M1Launch &L, hipStream_t st);
 

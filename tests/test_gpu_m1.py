@@ -80,8 +80,14 @@ def check_estimates(orc, plan, views, seed, dtype, samples_idx=None):
     return got
 
 
-def test_hashes_bit_exact(T, orc):
+@pytest.mark.parametrize("long_stream", [False, True])
+def test_hashes_bit_exact(T, orc, long_stream):
+    """Hash tables bit for bit against the oracle; with every stream of at most
+    64 indices (one thread per stream and sample) and with a stream of 100
+    (one block per stream and sample)."""
     nets = [W.triangle(8, seed=1), W.torus(L=2, D=3, seed=2), W.random_network(4, 5)]
+    if long_stream:
+        nets.append(W.ring(3, 100, seed=6))
     for m in (1, 64, 16384):
         plan, views = make_plan(T, nets, "float32", m, 6, 1234)
         tab = plan.hashes().cpu().numpy()
