@@ -324,64 +324,88 @@ __device__ __forceinline__ void gather_pair(const M2Node &nd, const int32_t *tab
 // Hash coefficients of tensor nd for one sample: child contractions [0, c),
 // tensor sketches [c, c + 2(qt-1)), padding slots after that; thread tid < c +
 // 2(qt-1) + (qt-c) writes coef[tid].
-__device__ __forceinline__ void node_coeffs(const M2Node &nd, uint64_t sample, HashCoeffs *coef) {
-  const int tid = threadIdx.x, c = nd.nchild, qt = nd.qt, n_t = 2 * (qt - 1);
-  if (tid >= c + n_t + (qt - c)) return;
-  uint64_t stream;
-  if (tid < c) {
-    stream = (uint64_t)nd.child_edge[tid];
-  } else if (tid < c + n_t) {
-    const int k = tid - c, tix = k >> 1, d = k & 1;
+// Stream id of coefficient slot j of tensor nd (layout as in node_coeffs).
+__device__ __forceinline__ uint64_t node_stream(const M2Node &nd, int j) {
+  const int c = nd.nchild, qt = nd.qt, n_t = 2 * (qt - 1);
+  if (j < c) return (uint64_t)nd.child_edge[j];
+  if (j < c + n_t) {
+    const int k = j - c, tix = k >> 1, d = k & 1;
     // tix enumerates (level l, index j) level-major from l = qt: tix = qt - l + j
     int l = qt, base = 0;
     while (tix - base >= l / 2) { base += l / 2; l /= 2; }
-    stream = (1ull << 62) + ((uint64_t)nd.local << 32) + ((uint64_t)l << 16) + (uint64_t)(2 * (tix - base) + d);
-  } else {
-    stream = (1ull << 63) + ((uint64_t)nd.local << 32) + (uint64_t)(c + tid - c - n_t);
+    return (1ull << 62) + ((uint64_t)nd.local << 32) + ((uint64_t)l << 16) + (uint64_t)(2 * (tix - base) + d);
   }
-  coef[tid] = hash_coeffs(nd.seed, sample, stream);
+  return (1ull << 63) + ((uint64_t)nd.local << 32) + (uint64_t)(c + j - c - n_t);
 }
 
-// Level-one slot tables of every (tensor with children, sample), one wave per
-// pair: the child (or padding) count sketch of each slot, combined with the
+__device__ __forceinline__ void node_coeffs(const M2Node &nd, uint64_t sample, HashCoeffs *coef) {
+  const int tid = threadIdx.x, c = nd.nchild, qt = nd.qt, n_t = 2 * (qt - 1);
+  if (tid >= c + n_t + (qt - c)) return;
+  coef[tid] = hash_coeffs(nd.seed, sample, node_stream(nd, tid));
+}
+
+// Level-one slot tables of every (tensor with children, sample): the child
+// (or padding) count sketch of each slot, combined with the
 // first tensor sketch of its pair when qt >= 2 (Algorithm 4's first level),
 // packed as bucket | sign << 31.  out: [tensor of `list`][sample][tcap], `list`
 // holding the tensors of every depth (the gather of depth d reads from its
 // offset).  Computed apart from the gathers, in one launch per estimate, so
 // that the serial hash arithmetic of one sample does not hold up the LDS work
 // of another.
-constexpr int kTabThreads = 64;
+constexpr int kTabThreads = 256, kTabSamples = 32;  // samples per block
 
+// One block per (tensor, run of kTabSamples samples): first the hash
+// coefficients of every (sample, stream) pair, one per thread (a sample's pairs
+// are few, so a block per sample left most lanes idle), then every slot-table
+// entry of the run's samples.
 __global__ __launch_bounds__(kTabThreads) void m2_tables_kernel(const M2Node *__restrict__ nodes,
                                                                 const int32_t *__restrict__ list,
                                                                 const int32_t *__restrict__ tables, int64_t W,
                                                                 int64_t sample0, int64_t n_samples, int log2m,
                                                                 uint32_t *__restrict__ out, int tcap) {
-  __shared__ HashCoeffs coef[3 * kM2MaxChildren];
+  constexpr int NCO = 3 * kM2MaxChildren;
+  __shared__ HashCoeffs coef[kTabSamples][NCO];
+  __shared__ int32_t base_of[kM2MaxChildren + 1];
   const M2Node &nd = nodes[list[blockIdx.x]];
-  const int64_t s = blockIdx.y;
+  const int64_t s0 = (int64_t)blockIdx.y * kTabSamples;
+  const int ns = (int)min((int64_t)kTabSamples, n_samples - s0);
   const int tid = threadIdx.x, c = nd.nchild, qt = nd.qt, n_t = 2 * (qt - 1);
+  const int nco = c + n_t + (qt - c);
   const uint32_t m = 1u << log2m, mask = m - 1;
-  const int32_t *tab = tables ? tables + s * W : nullptr;
-  if (!tab) node_coeffs(nd, (uint64_t)(sample0 + s), coef);  // at most 3 * 8 <= 64 streams
-  __syncthreads();
-  uint32_t *row = out + ((int64_t)blockIdx.x * n_samples + s) * tcap;
-  int base = 0;
-  for (int j = 0; j < qt; ++j) {
-    const int nj = j < c ? nd.child_dim[j] : 1;
-    for (int i = tid; i < nj; i += kTabThreads) {
-      uint32_t v;
-      if (j < c)
-        v = tab ? (uint32_t)tab[nd.child_tab[j] + i] : hash_packed(coef[j], (uint32_t)i, mask);
-      else
-        v = tab ? (uint32_t)tab[nd.pad_tab[j]] : hash_packed(coef[c + n_t + (j - c)], 0u, mask);
-      if (qt >= 2) {
-        const uint32_t t = tsketch(nd, tab, coef, c, m, mask, j >> 1, j & 1, v & 0x7fffffffu);
-        v = (t & 0x7fffffffu) | ((v ^ t) & 0x80000000u);
-      }
-      row[base + i] = v;
+  if (!tables) {
+    for (int i = tid; i < ns * nco; i += kTabThreads) {
+      const int sl = i / nco, j = i - sl * nco;
+      coef[sl][j] = hash_coeffs(nd.seed, (uint64_t)(sample0 + s0 + sl), node_stream(nd, j));
     }
-    base += nj;
+  }
+  if (tid == 0) {
+    int b = 0;
+    for (int j = 0; j < qt; ++j) {
+      base_of[j] = b;
+      b += j < c ? nd.child_dim[j] : 1;
+    }
+    base_of[qt] = b;
+  }
+  __syncthreads();
+  const int n_ent = base_of[qt];
+  for (int i = tid; i < ns * n_ent; i += kTabThreads) {
+    const int sl = i / n_ent, e = i - sl * n_ent;
+    int j = 0;
+    while (e >= base_of[j + 1]) ++j;
+    const int ii = e - base_of[j];
+    const int64_t s = s0 + sl;
+    const int32_t *tab = tables ? tables + s * W : nullptr;
+    const HashCoeffs *cf = coef[sl];
+    uint32_t v;
+    if (j < c)
+      v = tab ? (uint32_t)tab[nd.child_tab[j] + ii] : hash_packed(cf[j], (uint32_t)ii, mask);
+    else
+      v = tab ? (uint32_t)tab[nd.pad_tab[j]] : hash_packed(cf[c + n_t + (j - c)], 0u, mask);
+    if (qt >= 2) {
+      const uint32_t t = tsketch(nd, tab, cf, c, m, mask, j >> 1, j & 1, v & 0x7fffffffu);
+      v = (t & 0x7fffffffu) | ((v ^ t) & 0x80000000u);
+    }
+    out[((int64_t)blockIdx.x * n_samples + s) * tcap + e] = v;
   }
 }
 
@@ -978,7 +1002,8 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     hipEvent_t ev = nullptr;
     int rc;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_HASH)) != TN_OK) return rc;
-    hipLaunchKernelGGL(m2_tables_kernel, dim3((unsigned)P->all_nodes.size(), (unsigned)n), dim3(kTabThreads), 0, st,
+    hipLaunchKernelGGL(m2_tables_kernel, dim3((unsigned)P->all_nodes.size(), (unsigned)((n + kTabSamples - 1) / kTabSamples)),
+                       dim3(kTabThreads), 0, st,
                        P->d_nodes, P->d_all_nodes, tables, p->W, c0, n, p->log2m, P->d_ltab, P->tcap);
     TN_HIP_CHECK(hipGetLastError());
     if ((rc = prof_end(p, st, TN_KERNEL_HASH, ev)) != TN_OK) return rc;
