@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <cstdlib>
+#include <mutex>
 
 #include "plan.h"
 #include "m1_device.h"
@@ -383,20 +384,23 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
 // for the persistent kernel.
 struct TuneKey {
   int64_t slots, entries_hint, m, S, W;
-  int dtype;
+  int dtype, device;
   bool fused;
   bool operator==(const TuneKey &o) const {
     return slots == o.slots && entries_hint == o.entries_hint && m == o.m && S == o.S && W == o.W &&
-           dtype == o.dtype && fused == o.fused;
+           dtype == o.dtype && device == o.device && fused == o.fused;
   }
 };
+// Process-wide cache of tuned schedules; plans on several host threads may
+// tune at once, hence the lock (held only to look up or insert).
 static std::vector<std::pair<TuneKey, std::pair<int, int>>> g_tuned;
+static std::mutex g_tuned_mu;
 
 int m1_autotune(tn_plan *p, hipStream_t st) {
   if (p->log2m > kMaxLog2Acc) return TN_OK;  // bucket ranges: one schedule only
   int64_t entries = 0;
   for (const ScatterSlot &sl : p->h_slots) entries += (int64_t)sl.rows * sl.L;
-  const TuneKey key{(int64_t)p->h_slots.size(), entries, p->m, p->S, p->W, p->dtype, p->fused};
+  const TuneKey key{(int64_t)p->h_slots.size(), entries, p->m, p->S, p->W, p->dtype, p->device, p->fused};
   auto apply = [&](int sb, int banks) -> int {
     if (p->fused) return fused_configure(p, sb, banks);
     p->sb = sb;
@@ -404,8 +408,15 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
     p->scatter_lds = scatter_lds_for(p, sb);
     return TN_OK;
   };
-  for (const auto &kv : g_tuned)
-    if (kv.first == key) return apply(kv.second.first, kv.second.second);
+  {
+    std::pair<int, int> hit{0, 0};
+    {
+      std::lock_guard<std::mutex> lk(g_tuned_mu);
+      for (const auto &kv : g_tuned)
+        if (kv.first == key) hit = kv.second;
+    }
+    if (hit.first > 0) return apply(hit.first, hit.second);
+  }
   const int64_t n = std::min(p->fused ? p->fused_chunk_cap : p->chunk, p->S);
   const int32_t *tables = nullptr;
   int rc = m1_tables(p, 0, n, st, &tables);
@@ -496,7 +507,10 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
   (void)hipEventDestroy(e1);
   if (rc != TN_OK) return rc;
   if ((rc = apply(best.first, best.second)) != TN_OK) return rc;
-  g_tuned.push_back({key, best});
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    g_tuned.push_back({key, best});
+  }
   return TN_OK;
 }
 
