@@ -141,6 +141,24 @@ def test_torus_full_size(T, orc, m):
     check_estimates(orc, plan, views, 5, "float32")
 
 
+def test_torus_bench_schedule(T, orc, monkeypatch):
+    """The schedule the torus benchmark runs (four samples per pass, two banks,
+    512-thread blocks reading their column tables once, eight loads in flight)
+    on tori of the benchmark's seeds at full size, every sample against the
+    oracle; then the same plan autotuned agrees to the fixed-point resolution."""
+    monkeypatch.setenv("TN_SCATTER_SB", "4")
+    monkeypatch.setenv("TN_SCATTER_BANKS", "2")
+    nets = [W.torus(L=4, D=16, seed=2 + b) for b in range(3)]
+    plan, views = make_plan(T, nets, "float32", 1024, 8, 0)
+    assert plan.query(8) == 4 and plan.query(10) == 2
+    got = check_estimates(orc, plan, views, 0, "float32")
+    monkeypatch.delenv("TN_SCATTER_SB")
+    monkeypatch.delenv("TN_SCATTER_BANKS")
+    tuned, _ = make_plan(T, nets, "float32", 1024, 8, 0, flags=T.TN_FLAG_AUTOTUNE)
+    _, got2 = run(tuned)
+    assert np.all(np.abs(got2 - got) <= 1e-9 * np.abs(got).max())
+
+
 @pytest.mark.parametrize("m", [16384, 32768, 65536])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_torus_large_m(T, orc, m, dtype):

@@ -151,6 +151,33 @@ def test_caterpillar_full_size(T, orc):
     check(orc, plan, views, 0, "float32", samples=[0, 5, 15])
 
 
+@pytest.mark.parametrize("flags", ["fp64", "bf16"])
+def test_caterpillar_bench_schedule(T, orc, flags):
+    """The caterpillar at the benchmark's size and launch shape: S = 4096 samples
+    in one plan (column-split products, the gathers summing the partials, four
+    samples per gather block, the two-child gather kernel); sampled estimates,
+    including the last sample of a block and of the plan, against the oracle
+    (FP32 bar, or the BF16 products' bar of levels * 2^-7)."""
+    net = W.tt_caterpillar()
+    if flags == "fp64":
+        plan, views = make_plan(T, [net], "float32", 4096, 4096, 0)
+        check(orc, plan, views, 0, "float32", samples=[0, 3, 2047, 4095])
+        return
+    import torch
+    ts = [torch.from_numpy(np.ascontiguousarray(x)).cuda().float() for x in net.data]
+    view = net.with_data([t.double().cpu().numpy() for t in ts])
+    plan = T.Plan([T.NetworkSpec.from_network(net, ts)], T.TN_ACYCLIC, 4096, 4096, 0, root=0,
+                  flags=T.TN_FLAG_MFMA_BF16)
+    samples = torch.empty(4096, dtype=torch.float64, device="cuda")
+    plan.estimate(samples_out=samples)
+    torch.cuda.synchronize()
+    got = samples.cpu().numpy()
+    for r in (0, 3, 2047, 4095):
+        o = orc.m2_estimate(view, 4096, 0, r, root=0, want_trace=True)
+        scale = np.linalg.norm(o["x"][0]) * np.linalg.norm(o["r_root"])
+        assert abs(got[r] - o["estimate"]) <= 31 * 2.0 ** -7 * scale, r
+
+
 def test_injective_hashes_exact(T, orc):
     """Identity count sketches and collision-free tensor sketches injected through
     the test hook: Eq. (2) reproduces the exact contraction."""
