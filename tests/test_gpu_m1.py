@@ -233,6 +233,27 @@ def test_batched_random_networks(T, orc):
     check_estimates(orc, plan, views, 11, "float32")
 
 
+def test_batched_bench_shape(T, orc):
+    """The benchmark's batch: all 4096 random cyclic networks (29,912 tensors,
+    1.16 GB of FP32) in one autotuned plan, S = 16; sampled networks and
+    samples against the oracle, and the plan's statistics against its samples."""
+    import torch
+    nets = W.random_batch(count=4096, seed=4)
+    specs, views = [], []
+    for n in nets:
+        ts = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32) for x in n.data]
+        specs.append(T.NetworkSpec.from_network(n, ts))
+        views.append((n, ts))
+    plan = T.Plan(specs, T.TN_CYCLIC, 1024, 16, 0, flags=T.TN_FLAG_AUTOTUNE)
+    stats, got = run(plan)
+    for j in (0, 1, 2047, 4095):
+        n, ts = views[j]
+        v = n.with_data([t.double().cpu().numpy() for t in ts])
+        ref, scale = oracle_samples(orc, v, 1024, 0 + j, [0, 7, 15])
+        assert np.all(np.abs(got[j, [0, 7, 15]] - ref) <= TAU["float32"] * scale), j
+    assert np.allclose(stats[:, 0], got.mean(axis=1), rtol=1e-12, atol=0)
+
+
 @pytest.mark.parametrize("m,S", [(1, 3), (2, 5), (4, 7), (32, 1), (64, 17)])
 def test_edge_cases(T, orc, m, S):
     rng = np.random.default_rng(m + S)
