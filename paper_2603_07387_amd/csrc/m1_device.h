@@ -386,22 +386,68 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       }
     }
   } else {
+    // Rows whose length is not a multiple of VEC, or a slot that starts
+    // inside a 16-byte vector: the slot's flat entry range is read as aligned
+    // 16-byte vectors, each entry finding its own row and column.  The fewer
+    // than VEC entries before the first aligned vector and after the last one
+    // are read singly, one per thread, first.
     const T __attribute__((address_space(1))) *Xg =
         (const T __attribute__((address_space(1))) *)X;
-    for (uint32_t e0 = 0; e0 < N; e0 += NT * UNROLL) {
-      T buf[UNROLL];
+    const uint32_t head =
+        min(N, ((16u - ((uint32_t)reinterpret_cast<uintptr_t>(X) & 15u)) & 15u) / (uint32_t)sizeof(T));
+    const uint32_t NV = (N - head) / VEC, body = head + NV * VEC;
+    {
+      const uint32_t singles = head + (N - body);  // < 2 VEC <= NT
+      const uint32_t e = (uint32_t)tid < head ? (uint32_t)tid : body + ((uint32_t)tid - head);
+      const bool act = (uint32_t)tid < singles;
+      const double x = act ? (double)to_acc_any(Xg[e]) : 0.0;
+      update_scale(fabs(x));
+      if (act) {
+        const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
+        scatter_one(x, r, e - r * (uint32_t)L);
+      }
+    }
+    if (NV > 0) {  // uniform over the block
+      using V = typename Vec16<T>::type;
+      const V __attribute__((address_space(1))) *Xv =
+          (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X + head);
+      constexpr bool PREFETCH = NT >= 512;
+      V buf[UNROLL], nxt[UNROLL];
+      if constexpr (PREFETCH) {
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) buf[u] = Xg[min(e0 + u * NT + tid, N - 1)];
-      double lmax = 0.0;
+        for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
+      }
+      for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) lmax = fmax(lmax, fabs((double)to_acc_any(buf[u])));
-      update_scale(lmax);
+        for (int u = 0; u < UNROLL; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
+        double lmax = 0.0;
 #pragma unroll
-      for (int u = 0; u < UNROLL; ++u) {
-        const uint32_t e = e0 + u * NT + tid;
-        if (e < N) {
-          const uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
-          scatter_one((double)to_acc_any(buf[u]), r, e - r * (uint32_t)L);
+        for (int u = 0; u < UNROLL; ++u) {
+          const T *xs = reinterpret_cast<const T *>(&buf[u]);
+#pragma unroll
+          for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+        }
+        update_scale(lmax);
+        if (PREFETCH && v0 + NT * UNROLL < NV) {  // uniform over the block
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          if (v0 + u * NT + tid < NV) {
+            const uint32_t e = head + (v0 + u * NT + tid) * VEC;
+            uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
+            uint32_t c = e - r * (uint32_t)L;
+            const T *xs = reinterpret_cast<const T *>(&buf[u]);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+              scatter_one((double)to_acc_any(xs[i]), r, c);
+              if (++c == (uint32_t)L) {  // the vector runs on into the next row
+                c = 0;
+                ++r;
+              }
+            }
+          }
         }
       }
     }

@@ -80,6 +80,27 @@ def check_estimates(orc, plan, views, seed, dtype, samples_idx=None):
     return got
 
 
+def check_sketches(orc, plan, views, seed, dtype, first, count):
+    """Every bucket of every tensor's sketch in samples [first, first + count)
+    within tau * A_b, A_b being the same bucket of the sketch of |X| with all
+    signs +1 (an entry hashed to a wrong bucket, or with a wrong sign, moves
+    a bucket by about |x|, far beyond that bar)."""
+    got = plan.sketches(first=first, count=count).cpu().numpy()
+    k0 = 0
+    for j, net in enumerate(views):
+        absnet = net.with_data([np.abs(x) for x in net.data])
+        for r in range(first, first + count):
+            ref = orc.m1_estimate(net, plan.m, seed + j, r, want_sketches=True)["sketches"]
+            tables = []
+            for e in range(net.t):
+                h, _ = orc.hash_table(seed + j, r, e, net.dims[net.edges[e][0]], plan.m)
+                tables.append(np.concatenate([h, np.ones_like(h)]))
+            A = orc.m1_estimate(absnet, plan.m, 0, 0, tables=tables, want_sketches=True)["sketches"]
+            err = np.abs(got[r - first, k0:k0 + net.p] - ref)
+            assert np.all(err <= TAU[dtype] * A + 1e-300), (j, r, err.max())
+        k0 += net.p
+
+
 @pytest.mark.parametrize("long_stream", [False, True])
 def test_hashes_bit_exact(T, orc, long_stream):
     """Hash tables bit for bit against the oracle; with every stream of at most
@@ -252,6 +273,49 @@ def test_batched_bench_shape(T, orc):
         ref, scale = oracle_samples(orc, v, 1024, 0 + j, [0, 7, 15])
         assert np.all(np.abs(got[j, [0, 7, 15]] - ref) <= TAU["float32"] * scale), j
     assert np.allclose(stats[:, 0], got.mean(axis=1), rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("sb,banks", [(1, 1), (2, 1), (4, 2), (8, 1)])
+@pytest.mark.parametrize("dtype", ["float64", "float32", "bfloat16"])
+def test_rows_off_the_vector_grid(T, orc, monkeypatch, dtype, sb, banks):
+    """Rows of 37 entries (no whole number of 16-byte vectors) and slots that
+    start 0, 1 and 2 FP32 entries into a vector (rows 0, 1771 and 3542 of a
+    (40 x 100) x 37 tensor): the scatter's flat-vector path, whose vectors run
+    across rows and whose first and last partial vectors are read singly, at
+    several schedules, every sample against the oracle."""
+    monkeypatch.setenv("TN_SCATTER_SB", str(sb))
+    monkeypatch.setenv("TN_SCATTER_BANKS", str(banks))
+    rng = np.random.default_rng(11)
+    net = W.Network([3, 3], [40, 100, 37, 37, 100, 40], [(2, 3), (1, 4), (0, 5)],
+                    [rng.standard_normal((40, 100, 37)), rng.standard_normal((37, 100, 40))])
+    plan, views = make_plan(T, [net], dtype, 1024, 8, 21)
+    assert plan.query(8) <= sb
+    check_sketches(orc, plan, views, 21, dtype, 0, 8)
+    check_estimates(orc, plan, views, 21, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32", "bfloat16"])
+def test_misaligned_tensor_base(T, orc, dtype):
+    """Tensors that start 1 or 3 elements past a 16-byte boundary (views at a
+    storage offset): every slot takes the flat-vector path, including slots
+    shorter than their unaligned head (a 2 x 1 matrix), against the oracle."""
+    import torch
+    rng = np.random.default_rng(12)
+    shapes = [(2, 1), (1, 64), (64, 64), (64, 2)]
+    net = W.Network([2, 2, 2, 2], [2, 1, 1, 64, 64, 64, 64, 2], [(1, 2), (3, 4), (5, 6), (7, 0)],
+                    [rng.standard_normal(sh) for sh in shapes])
+    td = getattr(torch, dtype)
+    ts = []
+    for k, x in enumerate(net.data):
+        o = 1 + 2 * (k % 2)
+        buf = torch.zeros(x.size + o, dtype=td, device="cuda")
+        buf[o:] = torch.from_numpy(x.ravel()).to(td).cuda()
+        ts.append(buf[o:].view(x.shape))
+        assert ts[-1].data_ptr() % 16 != 0
+    plan = T.Plan([T.NetworkSpec.from_network(net, ts)], T.TN_CYCLIC, 256, 6, 3)
+    views = [net.with_data(host_view(ts))]
+    check_sketches(orc, plan, views, 3, dtype, 0, 6)
+    check_estimates(orc, plan, views, 3, dtype)
 
 
 @pytest.mark.parametrize("m,S", [(1, 3), (2, 5), (4, 7), (32, 1), (64, 17)])
