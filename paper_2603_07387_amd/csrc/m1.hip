@@ -35,17 +35,23 @@ using namespace m1dev;
 // (large m or many samples per pass), so that the CU still runs 16 waves.
 // RANGED (m above kMaxLog2Acc buckets): blockIdx.z selects the range of
 // 2^log2acc buckets the block accumulates (one bank, one sample per pass).
+// Fixed-point scale: with bound_in, slot b's entries are all below
+// bound_in[b] (a power of two, or 0 for an all-zero slot) and the scale is set
+// once; otherwise the block keeps a running maximum (a barrier per load round)
+// and, with bound_out, records the power-of-two bound it ends with.
+// Sample batch blockIdx.y + y0 of the launch's samples.
 template <typename T, typename A, int SB, int BANKS, bool RANGED = false, int NT = 256 * BANKS>
 __global__ __launch_bounds__(NT) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
-    int64_t samples, int log2m, int log2acc, int64_t n_slots, A *__restrict__ ybuf) {
+    int64_t samples, int log2m, int log2acc, int64_t n_slots, A *__restrict__ ybuf,
+    const double *__restrict__ bound_in, double *__restrict__ bound_out, int y0) {
   // No static LDS: the accumulators start at LDS address 0, so their offsets
   // need no base add per term.
   extern __shared__ __align__(16) unsigned char smem[];
   const ScatterSlot sl = slots[blockIdx.x];
   const int tid = threadIdx.x;
-  const int64_t s0 = (int64_t)blockIdx.y * SB;
+  const int64_t s0 = ((int64_t)blockIdx.y + y0) * SB;
   const int nsb = (int)min((int64_t)SB, samples - s0);
   const uint32_t m = 1u << log2m;
   const uint32_t ma = RANGED ? 1u << log2acc : m, amask = ma - 1;  // accumulator words per sample
@@ -63,8 +69,20 @@ __global__ __launch_bounds__(NT) void m1_scatter_kernel(
   const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
   FixedScale fs;
   fs.lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
+  if (bound_in != nullptr) {
+    const double b = bound_in[blockIdx.x];
+    if (b > 0.0) {
+      int e;
+      (void)frexp(b, &e);  // b = 2^(e - 1)
+      fs.scale = 62 - fs.lgN - (e - 1);
+      fs.sc = ldexp(1.0, fs.scale);
+      fs.bound = b;
+    }
+    fs.known = true;
+  }
   scatter_slot<T, SB, BANKS, NT, RANGED>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * ma, signbit,
                                          colt, rowt, s_max, fs, blockIdx.z, RANGED ? log2acc : -1);
+  if (bound_out != nullptr && tid == 0 && blockIdx.y == 0 && blockIdx.z == 0) bound_out[blockIdx.x] = fs.bound;
   const unsigned long long *neg = acc + signbit / 8;
   const int lga = RANGED ? log2acc : log2m;
   for (int i = tid; i < (nsb << lga); i += NT) {
@@ -460,11 +478,33 @@ int scatter_sb(const M1Launch &L, hipStream_t st) {
     if (L.lds_bytes > 65536)
       TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)L.lds_bytes));
-    dim3 grid((unsigned)L.n_slots, (unsigned)((L.samples + SB - 1) / SB),
-              ranged ? 1u << (L.log2m - kMaxLog2Acc) : 1u);
-    hipLaunchKernelGGL(kern, grid, dim3(ranged ? 1024 : wide ? kWideNT : 256 * L.banks), L.lds_bytes, st, L.slots, L.modes, L.data, L.tables,
-                       L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, reinterpret_cast<A *>(L.ybuf));
-    TN_HIP_CHECK(hipGetLastError());
+    // Slot bounds: without a bound array every block keeps a running
+    // maximum.  Else the first sample batch keeps one and records each slot's
+    // bound (when this launch is the first to see the data), and the other
+    // batches, in a second launch on the same stream, start from it.
+    const unsigned batches = (unsigned)((L.samples + SB - 1) / SB);
+    const unsigned z = ranged ? 1u << (L.log2m - kMaxLog2Acc) : 1u;
+    const dim3 block(ranged ? 1024 : wide ? kWideNT : 256 * L.banks);
+    A *y = reinterpret_cast<A *>(L.ybuf);
+    if (L.slot_bound == nullptr) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)L.n_slots, batches, z), block, L.lds_bytes, st, L.slots, L.modes,
+                         L.data, L.tables, L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, y, nullptr, nullptr, 0);
+      TN_HIP_CHECK(hipGetLastError());
+      return TN_OK;
+    }
+    int y0 = 0;
+    if (L.record_bound) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)L.n_slots, 1u, z), block, L.lds_bytes, st, L.slots, L.modes, L.data,
+                         L.tables, L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, y, nullptr, L.slot_bound, 0);
+      TN_HIP_CHECK(hipGetLastError());
+      y0 = 1;
+    }
+    if (batches > (unsigned)y0) {
+      hipLaunchKernelGGL(kern, dim3((unsigned)L.n_slots, batches - (unsigned)y0, z), block, L.lds_bytes, st,
+                         L.slots, L.modes, L.data, L.tables, L.W, L.samples, L.log2m, kMaxLog2Acc, L.n_slots, y,
+                         L.slot_bound, nullptr, y0);
+      TN_HIP_CHECK(hipGetLastError());
+    }
     return TN_OK;
   }
 }

@@ -96,6 +96,7 @@ struct FixedScale {
   double bound = 0.0;  // every |x| seen is < bound (0: none seen yet)
   int lgN = 11;        // >= ceil(log2(terms)) and >= 11
   int par = 0;         // parity of the double-buffered running maximum
+  bool known = false;  // bound given up front: no running maximum
 };
 
 // Layout of SB two-bank sketches of m words: positive banks of the SB samples
@@ -169,6 +170,7 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
   // iteration cannot race with the next iteration's update), then a rescale
   // when it reaches the bound.  Called by every thread once per iteration.
   auto update_scale = [&](double lmax) {
+    if (fs.known) return;  // uniform over the block
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
     if ((tid & 63) == 0) atomicMax(&s_max[fs.par], (unsigned long long)__double_as_longlong(lmax));

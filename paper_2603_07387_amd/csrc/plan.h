@@ -71,6 +71,7 @@ struct tn_plan {
   tn::NetDesc *d_nets = nullptr;
   void *d_tw = nullptr;
   void *d_ybuf = nullptr;
+  double *d_slot_bound = nullptr;  // [slots]: power-of-two bound of |x| (see M1Launch)
   bool two_pass = false;        // the m-point FFT does not fit in LDS: two-pass combine
   int64_t n_pairs = 0;          // its tensor pairs (two real sketches per complex transform)
   int32_t *d_pairs = nullptr;   // [n_pairs][2]: tensors a, b (or -1)

@@ -255,6 +255,7 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   unsigned char *yb = nullptr;
   if ((rc = dev_alloc(&yb, (size_t)chunk * p->h_slots.size() * (size_t)p->m * as)) != TN_OK) return rc;
   p->d_ybuf = yb;
+  if ((rc = dev_alloc(&p->d_slot_bound, p->h_slots.size())) != TN_OK) return rc;
   if (p->two_pass) {
     // the tensors of each network two by two (an odd one out alone)
     std::vector<int32_t> pairs, pair0;
@@ -358,6 +359,8 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
     L.log2m = p->log2m;
     L.lds_bytes = p->scatter_lds;
     L.ybuf = p->d_ybuf;
+    L.slot_bound = p->d_slot_bound;
+    L.record_bound = c0 == 0;  // the data may have changed since the last call
     hipEvent_t ev = nullptr;
     if ((rc = prof_begin(p, st, &ev, TN_KERNEL_SKETCH)) != TN_OK) return rc;
     if ((rc = launch_m1_scatter(L, st)) != TN_OK) return rc;
@@ -488,6 +491,8 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
             p->banks = banks;
             L.lds_bytes = scatter_lds_for(p, sb);
             L.ybuf = p->d_ybuf;
+            L.slot_bound = p->d_slot_bound;
+            L.record_bound = true;
             rc = launch_m1_scatter(L, st);
           }
         }
@@ -720,7 +725,7 @@ void plan_release(tn_plan *p) {
   void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data,    p->d_modes,
                   p->d_slots,   p->d_tslot,  p->d_nets,     p->d_tw,      p->d_ybuf,
                   p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn, p->d_cbuf, p->d_partial,
-                  p->d_pairs,   p->d_pair0};
+                  p->d_pairs,   p->d_pair0,  p->d_slot_bound};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p->d_streams = nullptr;
@@ -733,6 +738,7 @@ void plan_release(tn_plan *p) {
   p->d_tw = p->d_ybuf = p->d_cbuf = nullptr;
   p->d_partial = nullptr;
   p->d_pairs = p->d_pair0 = nullptr;
+  p->d_slot_bound = nullptr;
   p->d_est = nullptr;
   p->d_items = nullptr;
   p->d_counter = p->d_tensor_lgn = nullptr;
@@ -823,6 +829,8 @@ int plan_get_sketches(tn_plan *p, const tn_network *nets, int64_t first, int64_t
     L.log2m = p->log2m;
     L.lds_bytes = p->scatter_lds;
     L.ybuf = p->d_ybuf;
+    L.slot_bound = p->d_slot_bound;
+    L.record_bound = c0 == first;
     if ((rc = launch_m1_scatter(L, st)) != TN_OK) return rc;
     if ((rc = launch_m1_slots_to_tensors(p->d_tslot, p->n_tensors, p->dtype, p->d_ybuf,
                                          (int64_t)p->h_slots.size(), n, p->log2m,

@@ -98,6 +98,11 @@ struct M1Launch {
   int log2m;
   size_t lds_bytes;
   void *ybuf;                // [samples][n_slots][m] (double for F64, float otherwise)
+  // Per-slot power-of-two bound of |x| ([n_slots]; null: every block keeps a
+  // running maximum).  record_bound: this launch is the first to see the
+  // data, its first sample batch records the bounds the others then use.
+  double *slot_bound = nullptr;
+  bool record_bound = false;
 };
 
 // Persistent fused kernel: one work item = (network, first sample of a batch

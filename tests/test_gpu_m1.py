@@ -318,6 +318,24 @@ def test_misaligned_tensor_base(T, orc, dtype):
     check_estimates(orc, plan, views, 3, dtype)
 
 
+def test_bounds_follow_the_data(T, orc):
+    """The per-slot fixed-point bounds are taken again on every call: one plan
+    run on its tensors scaled in place (same pointers) by 2^-12, then 2^12 (a
+    stale bound would overflow the accumulators), then 1, every sample against
+    the oracle each time; and a call for later samples only (sketches of
+    samples 5..7) against the oracle's sketches."""
+    net = W.torus(L=2, D=8, seed=7)
+    ts = dev(net, "float32")
+    plan = T.Plan([T.NetworkSpec.from_network(net, ts)], T.TN_CYCLIC, 1024, 8, 9)
+    base = [t.clone() for t in ts]
+    for f in (2.0 ** -12, 2.0 ** 12, 1.0):
+        for t, b in zip(ts, base):
+            t.copy_(b * f)
+        views = [net.with_data(host_view(ts))]
+        check_estimates(orc, plan, views, 9, "float32")
+    check_sketches(orc, plan, views, 9, "float32", 5, 3)
+
+
 @pytest.mark.parametrize("m,S", [(1, 3), (2, 5), (4, 7), (32, 1), (64, 17)])
 def test_edge_cases(T, orc, m, S):
     rng = np.random.default_rng(m + S)
