@@ -406,6 +406,20 @@ def test_graph_replay(T, orc):
         del junk
 
 
+def test_graph_replay_after_data_change(T, orc):
+    """A replayed graph takes the slot bounds afresh: the tensors scaled in
+    place by 2^12 between replays (same pointers), every sample of both
+    replays against the oracle."""
+    net = W.torus(L=2, D=8, seed=5)
+    ts = dev(net, "float32")
+    plan = T.Plan([T.NetworkSpec.from_network(net, ts)], T.TN_CYCLIC, 256, 12, 4, flags=T.TN_FLAG_GRAPH)
+    base = [t.clone() for t in ts]
+    for f in (1.0, 2.0 ** 12):
+        for t, b in zip(ts, base):
+            t.copy_(b * f)
+        check_estimates(orc, plan, [net.with_data(host_view(ts))], 4, "float32")
+
+
 def test_bitwise_deterministic_across_schedules(T, orc, monkeypatch):
     """Fixed-point sketch accumulation: estimates are bit-identical run to run and
     for every samples-per-pass choice with one accumulator bank.  The two-bank
