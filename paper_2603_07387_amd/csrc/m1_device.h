@@ -168,7 +168,8 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
 
   // Block-wide running max of |x| (double-buffered so the read of one
   // iteration cannot race with the next iteration's update), then a rescale
-  // when it reaches the bound.  Called by every thread once per iteration.
+  // when it reaches the bound.  Called by every thread once per iteration,
+  // unless the block starts from a known bound.
   auto update_scale = [&](double lmax) {
     if (fs.known) return;  // uniform over the block
 #pragma unroll
@@ -278,14 +279,16 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
         for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
 #pragma unroll
           for (int u = 0; u < UNROLL; ++u) buf[u] = nxt[u];
-          double lmax = 0.0;
+          if (!fs.known) {  // running maximum of this load round (uniform over the block)
+            double lmax = 0.0;
 #pragma unroll
-          for (int u = 0; u < UNROLL; ++u) {
-            const T *xs = reinterpret_cast<const T *>(&buf[u]);
+            for (int u = 0; u < UNROLL; ++u) {
+              const T *xs = reinterpret_cast<const T *>(&buf[u]);
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+              for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+            }
+            update_scale(lmax);
           }
-          update_scale(lmax);
           if (v0 + NT * UNROLL < NV) {  // uniform over the block
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
@@ -335,28 +338,30 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       else
         vec_loop(std::false_type{});
     } else {
-          V buf[UNROLL], nxt[UNROLL];
+      V buf[UNROLL], nxt[UNROLL];
       if constexpr (PREFETCH) {
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
       }
       for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < UNROLL; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
-        double lmax = 0.0;
-  #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          const T *xs = reinterpret_cast<const T *>(&buf[u]);
-  #pragma unroll
-          for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+        if (!fs.known) {  // running maximum of this load round (uniform over the block)
+          double lmax = 0.0;
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            const T *xs = reinterpret_cast<const T *>(&buf[u]);
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+          }
+          update_scale(lmax);
         }
-        update_scale(lmax);
         if (PREFETCH && v0 + NT * UNROLL < NV) {  // uniform over the block
-  #pragma unroll
+#pragma unroll
           for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
         }
         uint32_t rr[UNROLL], cc[UNROLL];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           const uint32_t e = min(v0 + u * NT + tid, NV - 1) * VEC;  // clamped: valid table reads
           rr[u] = (L == 1) ? e : __umulhi(e, sl.magic);
@@ -366,21 +371,21 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
         // adds of vector u.
         uint32_t hv[2][SB], lv[2][SB][VEC];
         read_tabs(rr[0], cc[0], hv[0], lv[0]);
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           if (u + 1 < UNROLL) read_tabs(rr[u + 1], cc[u + 1], hv[(u + 1) & 1], lv[(u + 1) & 1]);
           if (v0 + u * NT + tid < NV) {
             const T *xs = reinterpret_cast<const T *>(&buf[u]);
             long long q[VEC], nq[VEC];
-  #pragma unroll
+#pragma unroll
             for (int i = 0; i < VEC; ++i) {
               q[i] = to_fixed((double)to_acc_any(xs[i]));
               nq[i] = BANKS == 2 ? 0 : -q[i];
             }
-  #pragma unroll
+#pragma unroll
             for (int s = 0; s < SB; ++s)
               if (s < nsb) {
-  #pragma unroll
+#pragma unroll
                 for (int i = 0; i < VEC; ++i) add_fixed(s, hv[u & 1][s], lv[u & 1][s][i], q[i], nq[i]);
               }
           }
@@ -422,14 +427,16 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
-        double lmax = 0.0;
+        if (!fs.known) {  // running maximum of this load round (uniform over the block)
+          double lmax = 0.0;
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          const T *xs = reinterpret_cast<const T *>(&buf[u]);
+          for (int u = 0; u < UNROLL; ++u) {
+            const T *xs = reinterpret_cast<const T *>(&buf[u]);
 #pragma unroll
-          for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+            for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
+          }
+          update_scale(lmax);
         }
-        update_scale(lmax);
         if (PREFETCH && v0 + NT * UNROLL < NV) {  // uniform over the block
 #pragma unroll
           for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
