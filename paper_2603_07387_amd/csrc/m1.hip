@@ -134,11 +134,53 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
 #pragma unroll
   for (int c = 0; c < NC; ++c) { pr[c] = 1.0; pi[c] = 0.0; }
 
+  // With one load round per pair (M <= NTH G), the first slot of each tensor
+  // of the next pair is loaded before this pair's transform: the loads stay
+  // in flight through the transform's LDS passes and barriers.
+  constexpr bool ONE_ROUND = M <= NTH * G;
+  A f1[G], f2[G];
+  auto first_slots = [&](int k) {
+    const bool pk = (k + 1) < nd.t1;
+    const int s1 = tslot[k], s2 = tslot[k + 1];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int b = g * NTH + tid;
+      f1[g] = y[(int64_t)s1 * M + (b < M ? b : 0)];
+      f2[g] = pk ? y[(int64_t)s2 * M + (b < M ? b : 0)] : (A)0;
+    }
+  };
+  if constexpr (ONE_ROUND)
+    if (nd.t0 < nd.t1) first_slots(nd.t0);
+
   for (int k = nd.t0; k < nd.t1; k += 2) {
     const bool pair = (k + 1) < nd.t1;
     const int a0 = tslot[k], a1 = tslot[k + 1];
     const int b1 = pair ? tslot[k + 2] : a1;
-    for (int b0 = 0; b0 < M; b0 += NTH * G) {
+    if constexpr (ONE_ROUND) {
+      A v1[G], v2[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) { v1[g] = f1[g]; v2[g] = f2[g]; }
+      for (int sl = a0 + 1; sl < a1; ++sl) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int b = g * NTH + tid;
+          v1[g] += y[(int64_t)sl * M + (b < M ? b : 0)];
+        }
+      }
+      for (int sl = a1 + 1; sl < b1; ++sl) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int b = g * NTH + tid;
+          v2[g] += y[(int64_t)sl * M + (b < M ? b : 0)];
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int b = g * NTH + tid;
+        if (b < M) z[pad32(bitrev<LOG2M>(b))] = A2{v1[g], v2[g]};
+      }
+    }
+    for (int b0 = 0; !ONE_ROUND && b0 < M; b0 += NTH * G) {
       A v1[G], v2[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) v1[g] = v2[g] = 0;
@@ -164,6 +206,8 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
       }
     }
     __syncthreads();
+    if constexpr (ONE_ROUND)
+      if (k + 2 < nd.t1) first_slots(k + 2);
     if constexpr (TWL)
       fft_lds<A, LOG2M, true, NTH>(z, t);
     else
