@@ -9,11 +9,12 @@ the combine and the per-network mean/variance, for every sample of every
 network in the batch.  Prints one JSON line.
 
 Workloads (all inputs seeded and synthetic):
+  batched   4096 random connected cyclic networks, 3-12 tensors, bonds
+            U{2..32}, FP32 N(0,1), cyclic estimator, m = 1024, S = 16
+            (1.16 GB resident).  Default.
   torus     4 x 4 periodic lattice of order-4 tensors, bond 16, FP32 U[0,1),
             cyclic estimator, m = 1024; a batch of B independent tori
-            (B = 256: 1 GiB resident).  Default.
-  batched   4096 random connected cyclic networks, 3-12 tensors, bonds
-            U{2..32}, FP32 N(0,1), cyclic estimator, m = 1024.
+            (B = 256: 1 GiB resident).
   ttcat     tensor-train caterpillar (32 cores (1,64,64)..(64,64,1) with their
             physical legs contracted against vectors), FP32 N(0,1/64), acyclic
             estimator, m = 4096, S = 4096 samples.
@@ -44,7 +45,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="torus", choices=["torus", "batched", "ttcat", "triangle"])
+    ap.add_argument("--workload", default="batched", choices=["torus", "batched", "ttcat", "triangle"])
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--batch", type=int, default=None)
@@ -55,7 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the unbatched comparison (one plan per network)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="seconds of oracle work per leg (one process, then all cores)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 5 device copies of 1 GiB (reference for HBM byte counters)")
     return ap.parse_args()
@@ -93,45 +95,76 @@ def build_workload(a):
     return nets, m, S, f"triangle64_fp64_normal_m{m}_x{B}", "float64", "cyclic"
 
 
-def _oracle_net(workload):
+def _oracle_net(workload, j):
+    """Network j of the workload as the oracle sees it (the batched workload's
+    networks differ; the other workloads repeat one network)."""
     import tn_workloads as W
-    return {"torus": lambda: W.torus(L=4, D=16, seed=2), "batched": lambda: W.random_network(4, 0),
-            "ttcat": lambda: W.tt_caterpillar(seed=3), "triangle": lambda: W.triangle(64, seed=1)}[workload]()
+    if workload == "batched":
+        return W.random_network(4, j)
+    return {"torus": lambda: W.torus(L=4, D=16, seed=2), "ttcat": lambda: W.tt_caterpillar(seed=3),
+            "triangle": lambda: W.triangle(64, seed=1)}[workload]()
 
 
 def _cpu_worker(args):
-    workload, m, samples = args
+    """Estimates of (network j, sample r) pairs until `seconds` of oracle time
+    have passed (building the networks' inputs is not counted)."""
+    workload, m, jobs, seconds = args
     import oracle
-    net = _oracle_net(workload)
-    t0 = time.perf_counter()
-    for r in samples:
+    done, spent = 0, 0.0
+    cache = {}
+    for (j, r) in jobs:
+        if j not in cache:
+            cache.clear()
+            cache[j] = _oracle_net(workload, j)
+        net = cache[j]
+        t0 = time.perf_counter()
         if workload == "ttcat":
-            oracle.m2_estimate(net, m, 0, r)
+            oracle.m2_estimate(net, m, j, r)
         else:
-            oracle.m1_estimate(net, m, 0, r, combine="dft")
-    return len(samples), time.perf_counter() - t0
+            oracle.m1_estimate(net, m, j, r, combine="dft")
+        spent += time.perf_counter() - t0
+        done += 1
+        if spent >= seconds:
+            break
+    return done, spent
 
 
-def cpu_baseline(workload, m, seconds):
-    """The FP64 oracle on the host cores (one process per core, each computing
-    sketch estimates of one network of the workload for about `seconds`)."""
+def _jobs(workload, S, worker, workers, count):
+    """(network, sample) pairs in the GPU's order: every sample of network 0,
+    then of network 1, ...  The batched workload's 4096 networks are split
+    into one contiguous run per worker; the other workloads have one network
+    and each worker takes its own run of samples."""
+    if workload == "batched":
+        start = worker * (4096 // workers) * S
+        return [((start + i) // S % 4096, (start + i) % S) for i in range(count)]
+    return [(0, worker * count + i) for i in range(count)]
+
+
+def cpu_baseline(workload, m, S, seconds):
+    """The FP64 oracle on the host cores: one process for `seconds`, then one
+    process per core (up to the box's share of 16) for `seconds` each, all on
+    the workload's (network, sample) pairs.  The rate of the parallel leg is
+    its estimates over the longest worker's oracle time."""
     import oracle
     oracle.build()
-    t0 = time.perf_counter()
-    _cpu_worker((workload, m, [0]))
-    one = max(time.perf_counter() - t0, 1e-6)
-    cores = max(1, min(16, os.cpu_count() or 1))
-    per = max(1, int(seconds / one))
-    jobs = [(workload, m, list(range(c * per, (c + 1) * per))) for c in range(cores)]
-    t0 = time.perf_counter()
+    nproc = os.cpu_count() or 1
+    cores = max(1, min(16, nproc))
+    cap = 1 << 20
+    n1, w1 = _cpu_worker((workload, m, _jobs(workload, S, 0, 1, cap), seconds))
+    jobs = [(workload, m, _jobs(workload, S, c, cores, cap), seconds) for c in range(cores)]
     with mp.get_context("spawn").Pool(cores) as pool:
         res = pool.map(_cpu_worker, jobs)
-    wall = time.perf_counter() - t0
     n = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
     how = "Method 2, Alg. 2-5" if workload == "ttcat" else "Eq. (1) with its DFT"
+    what = ("networks of the batch in order, S samples each" if workload == "batched"
+            else f"one {workload} network")
     return {"value": n / wall, "unit": "estimates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} estimates of one {workload} network (m={m}, FP64, {how}), "
-                      f"{per} per process on {cores} processes, {wall:.1f} s wall"}
+            "sample": f"{n} estimates ({what}; m={m}, FP64, {how}) on {cores} processes, "
+                      f"{wall:.1f} s of oracle time in the longest process",
+            "nproc": nproc,
+            "single_thread": {"value": n1 / w1, "unit": "estimates/s", "cores": 1,
+                              "sample": f"{n1} estimates ({what}) in {w1:.1f} s on one process"}}
 
 
 def source_hash(kernel_sources):
@@ -354,7 +387,7 @@ def main():
     }
     plan.close()
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(a.workload, m, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(a.workload, m, S, a.cpu_seconds)
     print(json.dumps(out))
 
 

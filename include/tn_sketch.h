@@ -36,6 +36,13 @@
  *
  * Packed hash entry (int32): bits 0..30 bucket h, bit 31 set when s = -1.
  *
+ * Buffers: the library trusts the pointers and sizes it is given.  Each data[k]
+ * must hold prod(dims of tensor k) entries of `dtype` in memory of the plan's
+ * device, and every output buffer must hold the element count its call states;
+ * neither is checked (the device reads and writes through them as given).  The
+ * Python binding checks device, dtype, contiguity and element counts before
+ * each call.
+ *
  * Errors: every entry point returns TN_OK (0) or a negative code; the text of
  * the last error on the calling thread is returned by tn_last_error().
  * Nothing throws across this boundary.  Validation runs on the host before any

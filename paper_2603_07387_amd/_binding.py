@@ -121,6 +121,27 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _on_current_device(t, what):
+    """Raise ValueError unless tensor t lives on the current HIP device (the
+    library reads and writes device memory only)."""
+    if not t.is_cuda:
+        raise ValueError(f"{what}: must be a device tensor, got {t.device}")
+    if torch.cuda.is_initialized() and t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{what}: on {t.device}, the current device is cuda:{torch.cuda.current_device()}")
+
+
+def _device_buffer(t, dtype, count, what):
+    """Check an output or input buffer: a contiguous device tensor of `dtype`
+    holding at least `count` elements."""
+    if t.dtype != dtype:
+        raise ValueError(f"{what}: dtype {t.dtype}, expected {dtype}")
+    if t.numel() < count:
+        raise ValueError(f"{what}: {t.numel()} elements, at least {count} needed")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: not contiguous")
+    _on_current_device(t, what)
+
+
 class NetworkSpec:
     """A tn_network: structure from (orders, dims, edges) and device tensors."""
 
@@ -144,14 +165,34 @@ class NetworkSpec:
     def from_network(cls, net, tensors=None, dtype=None):
         return cls(net.orders, net.dims, net.edges, tensors, dtype)
 
+    def sizes(self):
+        """Entries of each tensor: the product of its mode sizes."""
+        out, u = [], 0
+        for q in self.orders:
+            n = 1
+            for d in self.dims[u:u + q]:
+                n *= int(d)
+            out.append(n)
+            u += q
+        return out
+
     def bind(self, tensors):
+        """Bind device tensors.  The C ABI trusts the pointers it is given, so
+        every property it relies on is checked here first: one contiguous
+        tensor per network tensor, of the network dtype, holding exactly the
+        product of its mode sizes, on the current HIP device."""
         if len(tensors) != self.p:
             raise ValueError("one tensor per network tensor is required")
-        for t in tensors:
+        sizes = self.sizes()
+        for k, t in enumerate(tensors):
+            if t.dtype not in _DTYPES or _DTYPES[t.dtype] != self.dtype:
+                raise ValueError(f"tensor {k}: dtype {t.dtype} differs from the network dtype")
+            if t.numel() != sizes[k]:
+                raise ValueError(f"tensor {k}: {t.numel()} entries, its modes need {sizes[k]}")
             if not t.is_contiguous():
-                raise ValueError("tensors must be contiguous (row-major)")
-            if _DTYPES[t.dtype] != self.dtype:
-                raise ValueError("all tensors must share the network dtype")
+                raise ValueError(f"tensor {k}: not contiguous (row-major is required)")
+        for k, t in enumerate(tensors):
+            _on_current_device(t, f"tensor {k}")
         self.tensors = list(tensors)
         for k, t in enumerate(tensors):
             self._data[k] = t.data_ptr()
@@ -243,6 +284,7 @@ def median_of_means(samples, groups, stream=None):
     """Median of `groups` group means per row of a (n_nets, S) float64 device tensor."""
     if samples.dim() != 2 or samples.dtype != torch.float64 or not samples.is_contiguous():
         raise ValueError("samples must be a contiguous (n_nets, S) float64 tensor")
+    _on_current_device(samples, "samples")
     out = torch.empty(samples.shape[0], dtype=torch.float64, device=samples.device)
     tn_median_of_means(samples, samples.shape[0], samples.shape[1], groups, stream, out)
     return out
@@ -338,20 +380,32 @@ class MLP:
     def set_params(self, p):
         tn_mlp_set_params(self.handle, p)
 
+    def _rows(self, X, y=None):
+        """Check a feature batch (n, d_in) FP32 and its targets (n) FP32."""
+        if X.dim() != 2 or X.shape[1] != self.d_in:
+            raise ValueError(f"X must be (n, {self.d_in}), got {tuple(X.shape)}")
+        _device_buffer(X, torch.float32, X.shape[0] * self.d_in, "X")
+        if y is not None:
+            _device_buffer(y, torch.float32, X.shape[0], "y")
+
     def predict(self, X, stream=None):
+        self._rows(X)
         out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
         tn_mlp_predict(self.handle, X, stream, out)
         return out
 
     def grad(self, X, y, stream=None):
+        self._rows(X, y)
         g = torch.empty(self.num_params, dtype=torch.float32, device=X.device)
         loss = tn_mlp_grad(self.handle, X, y, stream, g)
         return g, loss
 
     def step(self, X, y, lr, stream=None):
+        self._rows(X, y)
         tn_mlp_step(self.handle, X, y, lr, stream)
 
     def train(self, X, y, batch=4096, epochs=100, lr=1e-3, stream=None):
+        self._rows(X, y)
         return tn_mlp_train(self.handle, X, y, batch, epochs, lr, stream)
 
     def close(self):
@@ -384,6 +438,9 @@ class Plan:
         dev = torch.device("cuda", torch.cuda.current_device())
         if stats is None:
             stats = torch.empty(2 * self.n_nets, dtype=torch.float64, device=dev)
+        _device_buffer(stats, torch.float64, 2 * self.n_nets, "stats")
+        if samples_out is not None:
+            _device_buffer(samples_out, torch.float64, self.n_nets * self.S, "samples_out")
         tn_sketch_estimate(self.handle, self._arr, stream, stats, samples_out)
         return stats
 
@@ -395,6 +452,8 @@ class Plan:
         return out.view(count, W)
 
     def set_hashes(self, tables, stream=None):
+        if tables is not None:
+            _device_buffer(tables, torch.int32, self.S * self.query(0), "hash tables")
         tn_plan_set_hashes(self.handle, tables, stream)
 
     def sketches(self, first=0, count=1, stream=None):

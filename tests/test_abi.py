@@ -87,3 +87,32 @@ def test_exact_validation(T):
     with pytest.raises(T.TNError) as ei:
         T.tn_contract_exact(_spec(T, W.Network([2, 2], [3, 3, 3, 3], [(0, 2)])))
     assert ei.value.code == T.TN_ERR_PARTIAL
+
+
+def test_binding_rejects_bad_buffers(T):
+    """The C ABI trusts the device pointers and sizes it is given; the binding
+    checks them before any call: host tensors, tensors whose entry count is not
+    the product of their mode sizes, wrong dtypes and non-contiguous views are
+    refused with ValueError (no device work is queued)."""
+    import torch
+    net = W.triangle(4)
+    with pytest.raises(ValueError, match="entries"):
+        T.NetworkSpec.from_network(net, [torch.zeros(16, dtype=torch.float64),
+                                         torch.zeros(15, dtype=torch.float64),
+                                         torch.zeros(16, dtype=torch.float64)])
+    with pytest.raises(ValueError, match="device"):
+        T.NetworkSpec.from_network(net, [torch.zeros(4, 4, dtype=torch.float64) for _ in range(3)])
+    with pytest.raises(ValueError, match="dtype"):
+        T.NetworkSpec.from_network(net, [torch.zeros(4, 4, dtype=torch.float64),
+                                         torch.zeros(4, 4, dtype=torch.float32),
+                                         torch.zeros(4, 4, dtype=torch.float64)])
+    with pytest.raises(ValueError, match="contiguous"):
+        T.NetworkSpec.from_network(net, [torch.zeros(4, 4, dtype=torch.float64).t() if k == 1 else
+                                         torch.zeros(4, 4, dtype=torch.float64) for k in range(3)])
+    from paper_2603_07387_amd._binding import _device_buffer
+    with pytest.raises(ValueError, match="at least"):
+        _device_buffer(torch.zeros(3, dtype=torch.float64), torch.float64, 4, "stats")
+    with pytest.raises(ValueError, match="device"):
+        _device_buffer(torch.zeros(4, dtype=torch.float64), torch.float64, 4, "stats")
+    with pytest.raises(ValueError):
+        T.median_of_means(torch.zeros(2, 8, dtype=torch.float64), 2)

@@ -192,6 +192,19 @@ def test_torus_large_m(T, orc, m, dtype):
     check_estimates(orc, plan, views, 5, dtype)
 
 
+def test_m8192_fp64_odd_networks_and_slots(T, orc):
+    """FP64 sketches at m = 8192: the in-LDS combine at its largest FP64 size
+    (1024 threads, two-level twiddles, the next pair's first slots loaded during
+    the current transform), with odd tensor counts and a tensor cut into
+    several slots, against the oracle per sample."""
+    big = W.Network([3, 3], [50, 40, 60, 60, 40, 50], [(0, 5), (1, 4), (2, 3)],
+                    [np.random.default_rng(5).standard_normal((50, 40, 60)),
+                     np.random.default_rng(6).standard_normal((60, 40, 50))])
+    nets = [W.triangle(24, seed=7), W.ring(5, 10, seed=8), W.random_network(7, 6, dtype=np.float64), big]
+    plan, views = make_plan(T, nets, "float64", 8192, 3, 41)
+    check_estimates(orc, plan, views, 41, "float64")
+
+
 @pytest.mark.parametrize("m", [8192, 16384, 32768, 65536])
 def test_large_m_odd_networks_fp32(T, orc, m):
     """FP32 sketches at large m with odd tensor counts (a tensor alone in its
@@ -421,39 +434,49 @@ def test_graph_replay_after_data_change(T, orc):
 
 
 def test_bitwise_deterministic_across_schedules(T, orc, monkeypatch):
-    """Fixed-point sketch accumulation: estimates are bit-identical run to run and
-    for every samples-per-pass choice with one accumulator bank.  The two-bank
-    layout (512-thread blocks) may rescale its accumulators at other points and
-    shifts the two banks separately, so it agrees to the fixed-point resolution
-    (2^-46 of the slot's max |x| per term), far inside the oracle bar."""
-    nets = [W.torus(L=2, D=16, seed=9), W.random_network(4, 3)]
-    monkeypatch.setenv("TN_SCATTER_BANKS", "1")
-    runs = []
-    for sb in ("1", "2", "4", "8"):
-        monkeypatch.setenv("TN_SCATTER_SB", sb)
-        p, views = make_plan(T, nets, "float32", 1024, 24, 8)
-        assert p.query(8) == int(sb) and p.query(10) == 1
-        _, g = run(p)
-        _, g2 = run(p)
-        assert np.array_equal(g, g2)
-        runs.append(g)
-    for g in runs[1:]:
-        assert np.array_equal(runs[0], g)
-    monkeypatch.delenv("TN_SCATTER_SB")
-    monkeypatch.setenv("TN_SCATTER_BANKS", "2")
-    p2, _ = make_plan(T, nets, "float32", 1024, 24, 8)
-    assert p2.query(10) == 2
-    _, g2b = run(p2)
+    """Fixed-point sketch accumulation.  Every sample batch of an estimate call
+    after the first starts from the slot bounds the first batch recorded, so its
+    sketches are exact integer sums at one fixed scale: bit-identical run to run
+    and for every samples-per-pass choice and accumulator layout.  The first
+    batch keeps a running maximum; where the maximum grows after a block's first
+    load round it rescales its accumulators, at points that depend on the block
+    size and on which samples share the batch, so those samples agree to the
+    fixed-point resolution (2^-46 of the slot's max |x| per term) only.  The
+    second network holds an N(0,1) tensor of 8192 entries whose largest entry
+    sits at its end (a rescale after the first round); the first is a small
+    torus and a random network."""
+    rng = np.random.default_rng(17)
+    big = rng.standard_normal((64, 128))
+    big[-1, -1] = 8.0 * np.abs(big).max()
+    late_max = W.Network([2, 2], [64, 128, 128, 64], [(0, 3), (1, 2)], [big, rng.standard_normal((128, 64))])
+    nets = [W.torus(L=2, D=16, seed=9), W.random_network(4, 3), late_max]
+    S, first = 24, 8          # samples; the largest first batch (8 samples per pass)
+    runs = {}
+    for banks in ("1", "2"):
+        monkeypatch.setenv("TN_SCATTER_BANKS", banks)
+        for sb in ("1", "2", "4", "8"):
+            monkeypatch.setenv("TN_SCATTER_SB", sb)
+            p, views = make_plan(T, nets, "float32", 1024, S, 8)
+            assert p.query(8) == int(sb) and p.query(10) == int(banks)
+            _, g = run(p)
+            _, g2 = run(p)
+            assert np.array_equal(g, g2)
+            runs[(sb, banks)] = g
+    ref_run = runs[("1", "1")]
+    for key, g in runs.items():
+        assert np.array_equal(g[:, first:], ref_run[:, first:]), key
+        assert np.all(np.abs(g - ref_run) <= 1e-9 * np.abs(ref_run).max(axis=1, keepdims=True)), key
     for j, net in enumerate(views):
-        ref, scale = oracle_samples(orc, net, 1024, 8 + j, range(3))
-        assert np.all(np.abs(runs[0][j, :3] - ref) <= 1e-5 * scale)
-        assert np.all(np.abs(g2b[j, :3] - ref) <= 1e-5 * scale)
-        assert np.all(np.abs(g2b[j] - runs[0][j]) <= 1e-9 * np.abs(runs[0][j]).max())
+        ref, scale = oracle_samples(orc, net, 1024, 8 + j, [0, 1, first, S - 1])
+        for g in runs.values():
+            assert np.all(np.abs(g[j, [0, 1, first, S - 1]] - ref) <= 1e-5 * scale)
+    monkeypatch.delenv("TN_SCATTER_SB")
     monkeypatch.delenv("TN_SCATTER_BANKS")
-    b, _ = make_plan(T, nets, "float32", 1024, 24, 8, flags=T.TN_FLAG_AUTOTUNE)
+    b, _ = make_plan(T, nets, "float32", 1024, S, 8, flags=T.TN_FLAG_AUTOTUNE)
     _, gb = run(b)
     assert b.query(8) in (1, 2, 4, 8, 16) and b.query(10) in (1, 2)
-    assert np.all(np.abs(gb - runs[0]) <= 1e-9 * np.abs(runs[0]).max())
+    assert np.array_equal(gb[:, 16:], ref_run[:, 16:])
+    assert np.all(np.abs(gb - ref_run) <= 1e-9 * np.abs(ref_run).max(axis=1, keepdims=True))
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32", "bfloat16"])

@@ -102,3 +102,30 @@ def test_rejects_acyclic_and_large_m(T):
     with pytest.raises(T.TNError) as e:
         T.Plan([spec], T.TN_CYCLIC, 16384, 4, 1, flags=T.TN_FLAG_PERSISTENT)
     assert e.value.code == T.TN_ERR_UNSUPPORTED
+
+
+def test_batched_bench_shape_persistent(T, orc):
+    """The benchmark's batch in one persistent launch: all 4096 random cyclic
+    networks (1.16 GB of FP32) with TN_FLAG_PERSISTENT | TN_FLAG_AUTOTUNE, m =
+    1024, S = 16 (many work items, largest-first order, the sample chunking of
+    the fused kernel); sampled networks and samples against the oracle, and the
+    plan's statistics against its samples."""
+    import torch
+    nets = W.random_batch(count=4096, seed=4)
+    specs, views = [], []
+    for n in nets:
+        ts = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32) for x in n.data]
+        specs.append(T.NetworkSpec.from_network(n, ts))
+        views.append((n, ts))
+    plan = T.Plan(specs, T.TN_CYCLIC, 1024, 16, 0, flags=T.TN_FLAG_PERSISTENT | T.TN_FLAG_AUTOTUNE)
+    stats, got = run(plan)
+    assert plan.query(11) == 1
+    rng = np.random.default_rng(2)
+    for j in sorted({0, 1, 2047, 4095, *rng.integers(0, 4096, 6).tolist()}):
+        n, ts = views[j]
+        v = n.with_data([t.double().cpu().numpy() for t in ts])
+        ii = [0, 5, 15]
+        ref, scale = oracle_samples(orc, v, 1024, 0 + j, ii)
+        assert np.all(np.abs(got[j, ii] - ref) <= TAU["float32"] * scale), j
+    assert np.all(np.isfinite(got))
+    assert np.allclose(stats[:, 0], got.mean(axis=1), rtol=1e-12, atol=0)
