@@ -258,6 +258,23 @@ int tn_plan_kernel_time(tn_plan *plan, int32_t kind, double *ms, int64_t *launch
 int tn_tensor_stats(const tn_network *nets, int32_t n_nets, void *stream, double *out);
 
 /*
+ * tn_tensor_stats_noalloc -- tn_tensor_stats for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, hosts that forbid
+ * hipMalloc): the same statistics, computed by the same kernel in the same
+ * order (bit-identical results), with the pointer table, entry counts and
+ * output staging in a fixed device array of the library (1.5 MiB per device,
+ * held until the process ends) instead of per-call allocations.  It calls no
+ * hipMalloc, hipFree or other allocating routine.
+ * At most 32768 tensors over all networks, else TN_ERR_UNSUPPORTED (nothing
+ * is queued).  Every call on a device shares that device's array: calls that
+ * overlap on one device (from several host threads, or queued on different
+ * streams) race; the library serializes its host side, and each call
+ * synchronizes `stream` before returning.  out: HOST, 4 * total tensors
+ * doubles.
+ */
+int tn_tensor_stats_noalloc(const tn_network *nets, int32_t n_nets, void *stream, double *out);
+
+/*
  * tn_median_of_means -- the amplification of Theorem 1: per network, split its
  * S per-sample estimates (samples: DEVICE, n_nets * S doubles, network-major, as
  * written by tn_sketch_estimate's samples_out) into `groups` consecutive groups,

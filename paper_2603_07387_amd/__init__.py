@@ -16,5 +16,5 @@ from ._binding import (  # noqa: F401
     tn_plan_query, tn_plan_stream, tn_plan_get_hashes, tn_plan_set_hashes, tn_plan_get_sketches,
     tn_plan_kernel_time, MLP, tn_mlp_create, tn_mlp_num_params, tn_mlp_get_params,
     tn_mlp_set_params, tn_mlp_predict, tn_mlp_grad, tn_mlp_step, tn_mlp_train, tn_mlp_destroy,
-    tn_tensor_stats, tn_median_of_means, median_of_means,
+    tn_tensor_stats, tn_tensor_stats_noalloc, tn_median_of_means, median_of_means,
 )

@@ -276,6 +276,20 @@ def tn_tensor_stats(specs, stream=None):
     return out.reshape(nt, 4)
 
 
+def tn_tensor_stats_noalloc(specs, stream=None):
+    """tn_tensor_stats through the allocation-free entry point (fixed device
+    scratch of the library; at most 32768 tensors)."""
+    import numpy as np
+    L = load()
+    L.tn_tensor_stats_noalloc.argtypes = [ctypes.POINTER(tn_network), ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double)]
+    nt = sum(s.p for s in specs)
+    out = np.zeros(nt * 4, dtype=np.float64)
+    _check(L.tn_tensor_stats_noalloc(_array(specs), len(specs), _stream(stream),
+                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(nt, 4)
+
+
 def tn_median_of_means(samples, n_nets, S, groups, stream, out):
     return _check(load().tn_median_of_means(_ptr(samples), n_nets, S, groups, _stream(stream), _ptr(out)))
 
