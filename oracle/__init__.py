@@ -14,6 +14,11 @@ Functions (each cites the passage of arXiv 2603.07387 it follows):
   * ``m1_estimate``   -- Method 1, Eq. (1) / Algorithm 1, per sample
   * ``m1_enumerate``  -- exact mean/variance of Method 1 over all hash functions
   * ``m2_estimate``   -- Method 2, Eq. (2) / Algorithms 2-5, per sample
+  * ``xcorr_estimate``/``xcorr_enumerate`` -- the earlier cross-correlation
+                         estimator of Examples 2-3 (one count sketch per
+                         contraction on both modes, a chain of Def. 9
+                         cross-correlations), per sample and exactly
+  * ``circ_xcorr``    -- Def. 9
   * ``dft``/``fft``/``circ_conv`` -- Def. 8 and the DFT convention of Lemma 5's proof
   * ``mean_var``      -- Welford sample mean / unbiased variance
   * ``median_of_means`` -- the median amplification of Theorem 1
@@ -79,6 +84,10 @@ def lib():
         L.orc_dft.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int]
         L.orc_fft.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int]
         L.orc_circ_conv.argtypes = [ctypes.c_int64, dp, dp, dp]
+        L.orc_circ_xcorr.argtypes = [ctypes.c_int64, dp, dp, dp]
+        L.orc_xcorr_estimate.argtypes = net + [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
+                                               i64p, dp, dp, dp]
+        L.orc_xcorr_enumerate.argtypes = net + [ctypes.c_int64, dp, dp, i64p]
         L.orc_mean_var.argtypes = [ctypes.c_int64, dp, dp, dp]
         _lib = L
     return _lib
@@ -200,6 +209,42 @@ def m1_enumerate(net, m):
     return float(mean[0]), float(var[0]), int(cnt.value)
 
 
+def xcorr_estimate(net, m, seed, sample, tables=None, want_sketches=False, want_scale=False):
+    """One estimate of the earlier cross-correlation method (Examples 2-3): the
+    same count sketch C_e on both modes of contraction e, tensor sketches, and
+    e_1^T (y_1 star ... star y_p) with Def. 9 applied left to right."""
+    n = _Net(net)
+    est = np.zeros(1)
+    sk = np.zeros(net.p * m) if want_sketches else None
+    sc = np.zeros(1) if want_scale else None
+    tab = None
+    if tables is not None:
+        tab = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.int64) for t in tables]))
+    rc = lib().orc_xcorr_estimate(
+        *n.args(), m, seed, sample,
+        tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if tab is not None else None,
+        _dptr(est), _dptr(sk) if sk is not None else None, _dptr(sc) if sc is not None else None)
+    _check(rc, "xcorr_estimate")
+    out = {"estimate": float(est[0])}
+    if sk is not None:
+        out["sketches"] = sk.reshape(net.p, m)
+    if sc is not None:
+        out["scale"] = float(sc[0])
+    return out
+
+
+def xcorr_enumerate(net, m):
+    """Exact (mean, variance, count) of the cross-correlation estimator over
+    every fully random hash assignment."""
+    n = _Net(net)
+    mean = np.zeros(1)
+    var = np.zeros(1)
+    cnt = ctypes.c_int64(0)
+    _check(lib().orc_xcorr_enumerate(*n.args(), m, _dptr(mean), _dptr(var), ctypes.byref(cnt)),
+           "xcorr_enumerate")
+    return float(mean[0]), float(var[0]), int(cnt.value)
+
+
 def m2_estimate(net, m, seed, sample, root=0, want_trace=False, tables=None):
     """One Method-2 estimate (Algorithm 2).  With want_trace, also the sketch
     x_l of every tensor (x_o for the root) and r_o.  ``tables`` maps stream id ->
@@ -303,6 +348,14 @@ def circ_conv(x, y):
     y = np.ascontiguousarray(y, dtype=np.float64)
     out = np.zeros(len(x))
     lib().orc_circ_conv(len(x), _dptr(x), _dptr(y), _dptr(out))
+    return out
+
+
+def circ_xcorr(x, y):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = np.zeros(len(x))
+    lib().orc_circ_xcorr(len(x), _dptr(x), _dptr(y), _dptr(out))
     return out
 
 

@@ -451,6 +451,130 @@ int orc_m1_enumerate(int p, const int *order, const int64_t *dims, const double 
 }
 
 /* ------------------------------------------------------------------------- */
+/* The prior cross-correlation method (Examples 2-3 of the Methods section)   */
+/* ------------------------------------------------------------------------- */
+
+/* Circular cross-correlation (Def. 9, 0-based, real vectors):
+ * (x star y)_j = sum_i x_i y_{(i + j) mod m}. */
+void orc_circ_xcorr(int64_t m, const double *x, const double *y, double *out) {
+  for (int64_t j = 0; j < m; ++j) {
+    double s = 0.0;
+    for (int64_t i = 0; i < m; ++i) s += x[i] * y[(i + j) % m];
+    out[j] = s;
+  }
+}
+
+/*
+ * One estimate of the earlier cross-correlation estimator the Methods section
+ * compares against (Examples 2 and 3): contraction e draws one count sketch
+ * C_e (stream e of the hash family, or the injected tables as in
+ * orc_m1_estimate) that BOTH of its modes use -- no complement -- every tensor
+ * is sketched with the tensor sketch of its modes' count sketches, and the
+ * sketches are combined by a left-to-right chain of circular
+ * cross-correlations in tensor order, y_1 star y_2 star ... star y_p, whose
+ * first component is the estimate.  scale (may be NULL): the first-order
+ * rounding scale of the Fourier route, (1/m) sum_j sum_k U_k prod_{k' != k}
+ * |Y_k'[j]| with Y = F y and U_k = sum_i |X_k(i)| (conjugation does not change
+ * a magnitude).
+ */
+int orc_xcorr_estimate(int p, const int *order, const int64_t *dims, const double *const *data,
+                       int t, const int *edges, int64_t m, uint64_t seed, uint64_t sample,
+                       const int64_t *tables, double *est, double *sketches, double *scale) {
+  net_t N;
+  if (m < 1 || net_init(&N, p, order, dims, data, t, edges)) return -1;
+  int64_t **mh = calloc((size_t)N.q, sizeof(int64_t *));
+  int32_t **ms = calloc((size_t)N.q, sizeof(int32_t *));
+  int rc = 0;
+  const int64_t *tp = tables;
+  for (int e = 0; e < t && rc == 0; ++e) {
+    int u = edges[2 * e], v = edges[2 * e + 1];
+    int64_t n = dims[u];
+    if (dims[v] != n) { rc = -1; break; }
+    if (u == v || mh[u] || mh[v]) { rc = -3; break; }
+    mh[u] = malloc((size_t)n * sizeof(int64_t)); ms[u] = malloc((size_t)n * sizeof(int32_t));
+    mh[v] = malloc((size_t)n * sizeof(int64_t)); ms[v] = malloc((size_t)n * sizeof(int32_t));
+    if (tables) {
+      for (int64_t i = 0; i < n; ++i) { mh[u][i] = tp[i]; ms[u][i] = (int32_t)tp[n + i]; }
+      tp += 2 * n;
+    } else {
+      orc_count_sketch(seed, sample, (uint64_t)e, n, m, mh[u], ms[u]);
+    }
+    for (int64_t i = 0; i < n; ++i) { mh[v][i] = mh[u][i]; ms[v][i] = ms[u][i]; }  /* the same C_e */
+  }
+  for (int u = 0; u < N.q && rc == 0; ++u) if (!mh[u]) rc = -2;   /* free mode */
+  double *y = malloc((size_t)(p * m) * sizeof(double));
+  if (rc == 0) {
+    for (int k = 0; k < p; ++k) m1_sketch_tensor(&N, k, m, mh, ms, y + (int64_t)k * m);
+    if (sketches) memcpy(sketches, y, (size_t)(p * m) * sizeof(double));
+    double *w = malloc((size_t)m * sizeof(double)), *tmp = malloc((size_t)m * sizeof(double));
+    memcpy(w, y, (size_t)m * sizeof(double));
+    for (int k = 1; k < p; ++k) {
+      orc_circ_xcorr(m, w, y + (int64_t)k * m, tmp);
+      memcpy(w, tmp, (size_t)m * sizeof(double));
+    }
+    *est = w[0];
+    free(w); free(tmp);
+    if (scale) {
+      double *Yr = malloc((size_t)(p * m) * sizeof(double)), *Yi = malloc((size_t)(p * m) * sizeof(double));
+      double *zero = calloc((size_t)m, sizeof(double));
+      for (int k = 0; k < p; ++k) dft_any(m, y + (int64_t)k * m, zero, Yr + (int64_t)k * m, Yi + (int64_t)k * m, 0);
+      double acc = 0.0;
+      for (int k = 0; k < p; ++k) {
+        double U = 0.0;
+        int64_t sz = tensor_size(&N, k);
+        for (int64_t i = 0; i < sz; ++i) U += fabs(data[k][i]);
+        for (int64_t j = 0; j < m; ++j) {
+          double prod = U;
+          for (int kk = 0; kk < p; ++kk)
+            if (kk != k) prod *= hypot(Yr[kk * m + j], Yi[kk * m + j]);
+          acc += prod;
+        }
+      }
+      *scale = acc / (double)m;
+      free(Yr); free(Yi); free(zero);
+    }
+  }
+  for (int u = 0; u < N.q; ++u) { free(mh[u]); free(ms[u]); }
+  free(mh); free(ms); free(y);
+  return rc;
+}
+
+/* Exact mean and variance of the cross-correlation estimator over every fully
+ * random hash assignment (as orc_m1_enumerate does for Method 1). */
+int orc_xcorr_enumerate(int p, const int *order, const int64_t *dims, const double *const *data,
+                        int t, const int *edges, int64_t m, double *mean, double *var,
+                        int64_t *count) {
+  int64_t total = 1, width = 0;
+  for (int e = 0; e < t; ++e) {
+    int64_t n = dims[edges[2 * e]];
+    for (int64_t i = 0; i < n; ++i) { total *= 2 * m; if (total > 50000000) return -1; }
+    width += 2 * n;
+  }
+  int64_t *tables = malloc((size_t)width * sizeof(int64_t));
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t a = 0; a < total; ++a) {
+    int64_t code = a, pos = 0;
+    for (int e = 0; e < t; ++e) {
+      int64_t n = dims[edges[2 * e]];
+      for (int64_t i = 0; i < n; ++i) {
+        tables[pos + i] = code % m; code /= m;
+        tables[pos + n + i] = (code % 2) ? -1 : 1; code /= 2;
+      }
+      pos += 2 * n;
+    }
+    double est;
+    int rc = orc_xcorr_estimate(p, order, dims, data, t, edges, m, 0, 0, tables, &est, NULL, NULL);
+    if (rc) { free(tables); return rc; }
+    s1 += est; s2 += est * est;
+  }
+  *mean = s1 / (double)total;
+  *var = s2 / (double)total - (*mean) * (*mean);
+  *count = total;
+  free(tables);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Method 2 (acyclic networks): Eq. (2), Algorithms 2-5                      */
 /* ------------------------------------------------------------------------- */
 
