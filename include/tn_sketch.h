@@ -109,6 +109,19 @@ extern "C" {
                                    few microseconds of device time; the other kinds then read
                                    0 launches).  TN_ERR_ARG without TN_FLAG_PROFILE */
 
+#define TN_FLAG_PRIOR_XCORR 0x40u /* TN_CYCLIC only: run the earlier cross-correlation estimator the
+                                   paper compares against (Examples 2-3) instead of Eq. (1):
+                                   both modes of contraction e use the same count sketch C_e
+                                   (no complement), and the tensor sketches are combined by the
+                                   chain y_1 star y_2 star ... star y_p of circular
+                                   cross-correlations (Def. 9) in tensor order.  By Lemma 5 this
+                                   is Eq. (1)'s pipeline with every mode of tensor k (0-based)
+                                   given the complement bucket when p - 1 - k is odd.  Unbiased
+                                   when every contraction joins tensors of opposite parity (trees
+                                   in chain order, even rings); otherwise biased (the triangle of
+                                   Example 3).  A negative reference, not an estimator to use
+                                   (TN_ERR_UNSUPPORTED with TN_ACYCLIC) */
+
 /* Kernel kinds for tn_plan_kernel_time. */
 #define TN_KERNEL_HASH 0        /* count-sketch table generation */
 #define TN_KERNEL_SKETCH 1      /* sketching pass: cyclic scatter / acyclic leaf+SMVP sweep */
@@ -187,6 +200,38 @@ int tn_sketch_estimate(tn_plan *plan, const tn_network *nets, void *stream, doub
  */
 int tn_contract_exact(const tn_network *net, void *stream, double *out);
 
+/*
+ * tn_partial_plan -- partial TNC (Corollary 1) with the estimator of Eq. (1).
+ *   net     : one network (same layout as above) whose modes outside every
+ *             contraction are free (K' of Def. 1); each tensor must keep at
+ *             least one contracted mode (an outer factor is the caller's to
+ *             multiply in), else TN_ERR_UNSUPPORTED.
+ * The output Y has one entry per assignment of the free modes, row-major over
+ * the free modes in increasing global mode order (Def. 1), n_out = prod of
+ * their sizes <= 2^20 entries (tn_plan_query key 12; key 13 = free modes).
+ * Entry r is estimated by Eq. (1) on the full TNC of the sub-tensors X_k(s_k)
+ * at r's indices (the sub-tensors of the corollary's proof).  All entries of a
+ * sample share one draw of the count sketches (seed `seed`, stream e for
+ * contraction e, as network 0 of tn_sketch_plan): each entry is unbiased with
+ * Lemma 6's variance bound for its sub-tensors, so the summed variance is at
+ * most 3^t/m prod_k ||X_k||_F^2 as in the corollary's proof; the entries'
+ * errors are correlated.  Each tensor is read once per sample pass; a tensor
+ * whose free modes are not its leading modes is first copied into a plan
+ * buffer with them moved to the front (every estimate call, on `stream`).
+ *   m       : power of two, 1 <= m <= 16384 (8192 for TN_F64 data): the
+ *             combine's transform stays in LDS.
+ *   flags   : TN_FLAG_GRAPH, TN_FLAG_PROFILE, TN_FLAG_PROFILE_SKETCH,
+ *             TN_FLAG_AUTOTUNE, TN_FLAG_PRIOR_XCORR; others TN_ERR_ARG.
+ * Run it with tn_sketch_estimate(plan, net, stream, stats, samples_out):
+ * stats holds 2 n_out doubles (per entry: mean, unbiased variance), samples_out
+ * n_out S doubles (entry-major).  tn_plan_get_sketches exports one sketch per
+ * sub-tensor (tensor by tensor, sub-tensors in row-major order of the
+ * tensor's free modes; tn_plan_query key 6 counts them).
+ * Errors as tn_sketch_plan (no TN_ERR_PARTIAL).
+ */
+int tn_partial_plan(const tn_network *net, int64_t m, int64_t samples, uint64_t seed, uint32_t flags,
+                    tn_plan **out);
+
 /* Release a plan and its device memory (synchronizes the device first). NULL is ignored. */
 void tn_plan_destroy(tn_plan *plan);
 
@@ -197,10 +242,13 @@ const char *tn_last_error(void);
  * tn_plan_query -- plan sizes.  key: 0 = hash-table width W (packed entries per
  * sample), 1 = number of hash streams, 2 = S, 3 = m, 4 = n_nets,
  * 5 = total tensors, 6 = sketch-vector slots per sample
- * (one per tensor), 7 = method, 8 = samples sketched per pass over the data,
+ * (one per tensor; a partial plan: one per sub-tensor), 7 = method,
+ * 8 = samples sketched per pass over the data,
  * 9 = samples per launch (workspace chunk), 10 = accumulator banks per sketch
  * of the cyclic sketching pass (1 or 2; 0 for TN_ACYCLIC), 11 = 1 when the
- * persistent kernel runs the plan (TN_FLAG_PERSISTENT).  Keys 8 and 10 may
+ * persistent kernel runs the plan (TN_FLAG_PERSISTENT), 12 = estimates per
+ * sample (n_nets; a partial plan: its output entries), 13 = free modes of a
+ * partial plan (0 otherwise).  Keys 8 and 10 may
  * change after the first estimate of a TN_FLAG_AUTOTUNE plan.
  * Returns the value, or a negative code.
  */

@@ -29,6 +29,7 @@ TN_FLAG_AUTOTUNE = 0x4
 TN_FLAG_MFMA_BF16 = 0x8
 TN_FLAG_PERSISTENT = 0x10
 TN_FLAG_PROFILE_SKETCH = 0x20
+TN_FLAG_PRIOR_XCORR = 0x40
 TN_KERNEL_HASH, TN_KERNEL_SKETCH, TN_KERNEL_COMBINE, TN_KERNEL_STATS = 0, 1, 2, 3
 
 _DTYPES = {torch.float64: TN_F64, torch.float32: TN_F32, torch.bfloat16: TN_BF16}
@@ -95,6 +96,8 @@ def load():
     L.tn_plan_kernel_time.restype = ctypes.c_int
     L.tn_median_of_means.argtypes = [vp, i64, i64, i32, vp, vp]
     L.tn_median_of_means.restype = ctypes.c_int
+    L.tn_partial_plan.argtypes = [net_p, i64, i64, u64, u32, P(vp)]
+    L.tn_partial_plan.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -212,6 +215,14 @@ def tn_sketch_plan(specs, method, m, samples, seed, root=-1, flags=0):
     arr = specs if isinstance(specs, ctypes.Array) else _array(specs)
     handle = ctypes.c_void_p()
     _check(load().tn_sketch_plan(arr, len(arr), method, m, samples, seed, root, flags, ctypes.byref(handle)))
+    return handle
+
+
+def tn_partial_plan(spec, m, samples, seed, flags=0):
+    """Plan for a partial TNC (Corollary 1): one network with free modes."""
+    arr = spec if isinstance(spec, ctypes.Array) else _array([spec])
+    handle = ctypes.c_void_p()
+    _check(load().tn_partial_plan(arr, m, samples, seed, flags, ctypes.byref(handle)))
     return handle
 
 
@@ -492,3 +503,19 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class PartialPlan(Plan):
+    """A tn_partial_plan: estimates every entry of the output tensor over the
+    free modes (row-major in increasing mode order).  estimate() returns the
+    stats of n_out entries; out_shape gives the output tensor's shape."""
+
+    def __init__(self, spec, m, samples, seed, flags=0):
+        self.specs = [spec]
+        self._arr = _array(self.specs)
+        self.handle = tn_partial_plan(self._arr, m, samples, seed, flags)
+        self.n_nets = tn_plan_query(self.handle, 12)
+        self.S = samples
+        self.m = m
+        used = set(spec.edges)
+        self.out_shape = tuple(spec.dims[u] for u in range(len(spec.dims)) if u not in used)

@@ -30,7 +30,7 @@ void clear_error() { g_err[0] = '\0'; }
 
 const char *last_error() { return g_err; }
 
-int validate_network(const tn_network *n, int index, NetCheck *chk) {
+int validate_network(const tn_network *n, int index, NetCheck *chk, bool allow_free) {
   if (!n) return set_error(TN_ERR_ARG, "network %d: null", index);
   if (n->p < 1) return set_error(TN_ERR_ARG, "network %d: p = %d", index, n->p);
   if (!n->order || !n->dims || (n->t > 0 && !n->edges))
@@ -79,7 +79,7 @@ int validate_network(const tn_network *n, int index, NetCheck *chk) {
     chk->edge_of[u] = e;
     chk->edge_of[v] = e;
   }
-  for (int u = 0; u < q; ++u)
+  for (int u = 0; u < q && !allow_free; ++u)
     if (chk->edge_of[u] < 0)
       return set_error(TN_ERR_PARTIAL, "network %d: mode %d is not contracted (partial TNC)", index, u);
   return TN_OK;
@@ -125,8 +125,10 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
   if (m < 1 || (m & (m - 1)) != 0) return set_error(TN_ERR_ARG, "m = %lld is not a power of two", (long long)m);
   if (method != TN_CYCLIC && method != TN_ACYCLIC) return set_error(TN_ERR_ARG, "method %d", method);
   if (flags & ~(uint32_t)(TN_FLAG_GRAPH | TN_FLAG_PROFILE | TN_FLAG_AUTOTUNE | TN_FLAG_MFMA_BF16 |
-                          TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH))
+                          TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH | TN_FLAG_PRIOR_XCORR))
     return set_error(TN_ERR_ARG, "unknown flags 0x%x", flags);
+  if ((flags & TN_FLAG_PRIOR_XCORR) && method != TN_CYCLIC)
+    return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_PRIOR_XCORR applies to the cyclic method");
   if ((flags & TN_FLAG_PROFILE_SKETCH) && !(flags & TN_FLAG_PROFILE))
     return set_error(TN_ERR_ARG, "TN_FLAG_PROFILE_SKETCH needs TN_FLAG_PROFILE");
   if ((flags & TN_FLAG_PERSISTENT) && method != TN_CYCLIC)

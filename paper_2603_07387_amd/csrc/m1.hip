@@ -99,9 +99,13 @@ __global__ __launch_bounds__(NT) void m1_scatter_kernel(
 // The transform is held padded in LDS (pad32).  TWL: the half table of
 // twiddles is staged beside it (padded too); otherwise (no room for it) the
 // two-level table (Tw2) is.
+// Network j's tensors are the entries [nets[j].t0, nets[j].t1) of the slot
+// ranges: entry k's sketch is the sum of the slots [tbeg[k], tend[k]) (a
+// plan's tensors in order: tbeg = first slot of each tensor, tend = tbeg + 1;
+// a partial plan lists each entry's sub-tensors).
 template <typename A, int LOG2M, bool TWL, int NTH = 256>
 __global__ __launch_bounds__(NTH) void m1_combine_kernel(
-    const NetDesc *__restrict__ nets, const int32_t *__restrict__ tslot,
+    const NetDesc *__restrict__ nets, const int32_t *__restrict__ tbeg, const int32_t *__restrict__ tend,
     const A *__restrict__ ybuf, int64_t n_slots, int64_t sample0, int64_t S,
     const typename Cplx<A>::type *__restrict__ tw, double *__restrict__ est) {
   using A2 = typename Cplx<A>::type;
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
   A f1[G], f2[G];
   auto first_slots = [&](int k) {
     const bool pk = (k + 1) < nd.t1;
-    const int s1 = tslot[k], s2 = tslot[k + 1];
+    const int s1 = tbeg[k], s2 = pk ? tbeg[k + 1] : s1;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const int b = g * NTH + tid;
@@ -154,8 +158,9 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
 
   for (int k = nd.t0; k < nd.t1; k += 2) {
     const bool pair = (k + 1) < nd.t1;
-    const int a0 = tslot[k], a1 = tslot[k + 1];
-    const int b1 = pair ? tslot[k + 2] : a1;
+    // slots [a0, a1) of the first tensor of the pair, [b0, b1) of the second
+    const int a0 = tbeg[k], a1 = tend[k];
+    const int b0 = pair ? tbeg[k + 1] : 0, b1 = pair ? tend[k + 1] : 0;
     if constexpr (ONE_ROUND) {
       A v1[G], v2[G];
 #pragma unroll
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
           v1[g] += y[(int64_t)sl * M + (b < M ? b : 0)];
         }
       }
-      for (int sl = a1 + 1; sl < b1; ++sl) {
+      for (int sl = b0 + 1; sl < b1; ++sl) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
           const int b = g * NTH + tid;
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
         if (b < M) z[pad32(bitrev<LOG2M>(b))] = A2{v1[g], v2[g]};
       }
     }
-    for (int b0 = 0; !ONE_ROUND && b0 < M; b0 += NTH * G) {
+    for (int p0 = 0; !ONE_ROUND && p0 < M; p0 += NTH * G) {
       A v1[G], v2[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) v1[g] = v2[g] = 0;
@@ -188,20 +193,20 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
       for (int sl = a0; sl < a1; ++sl) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          const int b = b0 + g * NTH + tid;
+          const int b = p0 + g * NTH + tid;
           v1[g] += y[(int64_t)sl * M + (b < M ? b : 0)];
         }
       }
-      for (int sl = a1; sl < b1; ++sl) {
+      for (int sl = b0; sl < b1; ++sl) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          const int b = b0 + g * NTH + tid;
+          const int b = p0 + g * NTH + tid;
           v2[g] += y[(int64_t)sl * M + (b < M ? b : 0)];
         }
       }
 #pragma unroll
       for (int g = 0; g < G; ++g) {
-        const int b = b0 + g * NTH + tid;
+        const int b = p0 + g * NTH + tid;
         if (b < M) z[pad32(bitrev<LOG2M>(b))] = A2{v1[g], v2[g]};
       }
     }
@@ -566,7 +571,7 @@ int scatter_t(const M1Launch &L, hipStream_t st) {
 }
 
 template <typename A, int LOG2M>
-int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const void *ybuf,
+int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend, const void *ybuf,
               int64_t n_slots, int64_t samples, int64_t sample0, int64_t S, const void *tw,
               double *est, hipStream_t st) {
   using A2 = typename Cplx<A>::type;
@@ -585,7 +590,7 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const v
       TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds));
     dim3 grid((unsigned)n_nets, (unsigned)samples);
-    hipLaunchKernelGGL(kern, grid, dim3(NTH), lds, st, nets, tslot,
+    hipLaunchKernelGGL(kern, grid, dim3(NTH), lds, st, nets, tbeg, tend,
                        reinterpret_cast<const A *>(ybuf), n_slots, sample0, S,
                        reinterpret_cast<const A2 *>(tw), est);
     TN_HIP_CHECK(hipGetLastError());
@@ -623,11 +628,11 @@ int combine_big(int64_t n_nets, const int32_t *tslot, const int32_t *pairs, cons
 }
 
 template <typename A>
-int combine_t(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, const void *ybuf,
+int combine_t(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend, const void *ybuf,
               int64_t n_slots, int64_t samples, int64_t sample0, int64_t S, int log2m,
               const void *tw, double *est, hipStream_t st) {
 #define TN_COMBINE_CASE(LG) \
-  case LG: return combine_m<A, LG>(nets, n_nets, tslot, ybuf, n_slots, samples, sample0, S, tw, est, st);
+  case LG: return combine_m<A, LG>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, tw, est, st);
   switch (log2m) {
     TN_COMBINE_CASE(0) TN_COMBINE_CASE(1) TN_COMBINE_CASE(2) TN_COMBINE_CASE(3)
     TN_COMBINE_CASE(4) TN_COMBINE_CASE(5) TN_COMBINE_CASE(6) TN_COMBINE_CASE(7)
@@ -652,16 +657,14 @@ int launch_m1_scatter(const M1Launch &L, hipStream_t st) {
   }
 }
 
-int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tslot, int dtype,
+int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend, int dtype,
                       const void *ybuf, int64_t n_slots, int64_t samples, int64_t sample0,
                       int64_t S, int log2m, const void *tw, double *est, hipStream_t st) {
   if (n_nets == 0 || samples == 0) return TN_OK;
   if (samples > 65535) return set_error(TN_ERR_UNSUPPORTED, "combine: samples per launch");
   if (dtype == TN_F64)
-    return combine_t<double>(nets, n_nets, tslot, ybuf, n_slots, samples, sample0, S, log2m, tw,
-                             est, st);
-  return combine_t<float>(nets, n_nets, tslot, ybuf, n_slots, samples, sample0, S, log2m, tw, est,
-                          st);
+    return combine_t<double>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, log2m, tw, est, st);
+  return combine_t<float>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, log2m, tw, est, st);
 }
 
 int launch_m1_combine_big(int64_t n_nets, const int32_t *tslot, const int32_t *pairs, const int32_t *pair0,

@@ -20,7 +20,7 @@ struct NetCheck {
   std::vector<int32_t> tensor_of;  // per mode
 };
 
-int validate_network(const tn_network *n, int index, NetCheck *chk);
+int validate_network(const tn_network *n, int index, NetCheck *chk, bool allow_free = false);
 int validate_tree(const tn_network *n, int index, const NetCheck &chk);
 const char *last_error();
 
@@ -103,6 +103,30 @@ struct tn_plan {
   // per-sample estimates [n_nets][S]
   double *d_est = nullptr;
 
+  // partial TNC (Corollary 1; tn_partial_plan): the plan's "networks" are the
+  // n_out entries of the output tensor.  Tensor k of the caller's network
+  // becomes n_slices "virtual" tensors, the sub-tensors at each assignment of
+  // its free modes; a tensor whose free modes are not its leading modes is
+  // first copied with them moved to the front (perm_off into d_perm).
+  struct PartialTensor {
+    std::vector<int64_t> dims;   // the tensor's mode sizes
+    std::vector<uint8_t> free;   // per mode: 1 if not contracted
+    int64_t size = 0, slice = 0, n_slices = 1;
+    int32_t first_virtual = 0;
+    bool permute = false;
+    int64_t perm_off = -1;       // byte offset of its copy in d_perm
+    int32_t perm_index = -1;     // its entry in d_psrc
+  };
+  bool partial = false;
+  int64_t n_out = 0;
+  int32_t n_free = 0;
+  std::vector<PartialTensor> pt;
+  std::vector<const void *> psrc;  // bound source pointers of the permuted tensors
+  const void **d_psrc = nullptr;
+  void *d_perm = nullptr;
+  int32_t *d_cbeg = nullptr;  // combine: per (entry, tensor) first slot ...
+  int32_t *d_cend = nullptr;  // ... and end of slots
+
   // acyclic method
   tn::M2Plan *m2 = nullptr;
 
@@ -135,6 +159,18 @@ int plan_set_hashes(tn_plan *p, const int32_t *tables, hipStream_t st);
 int plan_get_sketches(tn_plan *p, const tn_network *nets, int64_t first, int64_t count,
                       hipStream_t st, double *out);
 int plan_bind(tn_plan *p, const tn_network *nets, hipStream_t st);
+// cyclic-method plan building blocks (plan.hip), shared with the partial planner
+int m1_check_m(tn_plan *p);
+int add_tensor_slots(tn_plan *p, int32_t gtensor, int32_t mode0, int q, const int64_t *dims, int64_t size,
+                     int net, int k);
+int m1_layout(tn_plan *p, const std::vector<NetCheck> *chk);
+int plan_common(tn_plan *p);
+int plan_alloc_tail(tn_plan *p);
+// partial TNC (partial.hip)
+int partial_build(tn_plan *p, const tn_network *net);
+int partial_bind(tn_plan *p, const tn_network *nets, hipStream_t st);
+int partial_prepare(tn_plan *p, hipStream_t st);
+void partial_release(tn_plan *p);
 int prof_begin(tn_plan *p, hipStream_t st, hipEvent_t *ev, int kind);
 int prof_end(tn_plan *p, hipStream_t st, int kind, hipEvent_t start);
 int plan_kernel_time(tn_plan *p, int kind, double *ms, int64_t *launches);

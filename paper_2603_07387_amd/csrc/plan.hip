@@ -88,17 +88,57 @@ int fused_configure(tn_plan *p, int sb, int banks) {
   return TN_OK;
 }
 
-int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &chk) {
+}  // namespace
+
+// Cut tensor `gtensor` (q modes at plan modes mode0.., sizes dims[0..q), `size`
+// entries) into scatter slots: a (rows x L) matrix view whose L <= kMaxCols
+// columns are its trailing modes, at most kMaxSlotEntries entries per slot.
+int add_tensor_slots(tn_plan *p, int32_t gtensor, int32_t mode0, int q, const int64_t *dims, int64_t size,
+                     int net, int k) {
+  int split = q;
+  int64_t L = 1;
+  while (split > 0 && L * dims[split - 1] <= kMaxCols) {
+    L *= dims[split - 1];
+    --split;
+  }
+  if (split == q)
+    return set_error(TN_ERR_UNSUPPORTED, "cyclic method: network %d tensor %d has a last mode of size %lld > %d",
+                     net, k, (long long)dims[q - 1], kMaxCols);
+  const int64_t R = size / L;
+  const int64_t rows_per = std::max<int64_t>(1, std::min<int64_t>(kMaxRowsPerSlot, kMaxSlotEntries / L));
+  p->h_tslot.push_back((int32_t)p->h_slots.size());
+  for (int64_t r0 = 0; r0 < R; r0 += rows_per) {
+    ScatterSlot sl{};
+    sl.tensor = gtensor;
+    sl.q = q;
+    sl.split = split;
+    sl.L = (int32_t)L;
+    sl.mode0 = mode0;
+    sl.rows = (int32_t)std::min<int64_t>(rows_per, R - r0);
+    sl.row0 = r0;
+    sl.magic = L > 1 ? (uint32_t)(((uint64_t)1 << 32) / (uint64_t)L + 1) : 0u;
+    p->h_slots.push_back(sl);
+  }
+  return TN_OK;
+}
+
+// The m-dependent limits of the cyclic method: m <= 2^16, and the combine's
+// FFT in LDS or (from 2^14 points) in two passes through HBM.
+int m1_check_m(tn_plan *p) {
   const size_t as = acc_size(p->dtype);
   if (p->log2m > kMaxLog2M1)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: m = %lld exceeds %d", (long long)p->m,
                      1 << kMaxLog2M1);
-  const bool big = p->log2m > kMaxLog2Acc;  // bucket ranges in the scatter
-  // The combine's m-point FFT in LDS, else in two passes through HBM (m >= 2^14).
   p->two_pass = (size_t)p->m * 2 * as > p->max_lds;
   if (p->two_pass && p->log2m < kMaxLog2Acc)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: the m-point FFT needs %zu bytes of LDS",
                      (size_t)p->m * 2 * as);
+  return TN_OK;
+}
+
+int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &chk) {
+  int rc0 = m1_check_m(p);
+  if (rc0 != TN_OK) return rc0;
   int64_t gmode = 0, gtensor = 0;
   for (int j = 0; j < p->n_nets; ++j) {
     const tn_network &n = nets[j];
@@ -122,40 +162,33 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
       ModeDesc md{};
       md.table_off = stream_off[(size_t)e];
       md.n = (int32_t)n.dims[u];
-      md.comp = (n.edges[2 * e + 1] == u) ? 1 : 0;
+      // Eq. (1): the second mode of each contraction takes the complement
+      // (Def. 14).  The earlier cross-correlation chain instead conjugates the
+      // whole spectrum of every tensor at an odd distance from the last one,
+      // which by Lemma 5 is the complement on all of that tensor's modes.
+      if (p->flags & TN_FLAG_PRIOR_XCORR)
+        md.comp = ((n.p - 1 - c.tensor_of[(size_t)u]) & 1) ? 1 : 0;
+      else
+        md.comp = (n.edges[2 * e + 1] == u) ? 1 : 0;
       p->h_modes.push_back(md);
     }
     for (int k = 0; k < n.p; ++k, ++gtensor) {
-      const int q = n.order[k];
       const int32_t mode0 = (int32_t)(gmode + c.offsets[(size_t)k]);
-      int split = q;
-      int64_t L = 1;
-      while (split > 0 && L * n.dims[c.offsets[(size_t)k] + split - 1] <= kMaxCols) {
-        L *= n.dims[c.offsets[(size_t)k] + split - 1];
-        --split;
-      }
-      if (split == q)
-        return set_error(TN_ERR_UNSUPPORTED,
-                         "cyclic method: network %d tensor %d has a last mode of size %lld > %d", j,
-                         k, (long long)n.dims[c.offsets[(size_t)k] + q - 1], kMaxCols);
-      const int64_t R = c.sizes[(size_t)k] / L;
-      const int64_t rows_per = std::max<int64_t>(1, std::min<int64_t>(kMaxRowsPerSlot, kMaxSlotEntries / L));
-      p->h_tslot.push_back((int32_t)p->h_slots.size());
-      for (int64_t r0 = 0; r0 < R; r0 += rows_per) {
-        ScatterSlot sl{};
-        sl.tensor = (int32_t)gtensor;
-        sl.q = q;
-        sl.split = split;
-        sl.L = (int32_t)L;
-        sl.mode0 = mode0;
-        sl.rows = (int32_t)std::min<int64_t>(rows_per, R - r0);
-        sl.row0 = r0;
-        sl.magic = L > 1 ? (uint32_t)(((uint64_t)1 << 32) / (uint64_t)L + 1) : 0u;
-        p->h_slots.push_back(sl);
-      }
+      const int rc = add_tensor_slots(p, (int32_t)gtensor, mode0, n.order[k], n.dims + c.offsets[(size_t)k],
+                                      c.sizes[(size_t)k], j, k);
+      if (rc != TN_OK) return rc;
     }
     gmode += c.q;
   }
+  return m1_layout(p, &chk);
+}
+
+// Schedule, workspace and device tables of a cyclic plan whose slots, modes,
+// streams and networks are in place.  chk (the networks' checks) is needed by
+// the persistent kernel only.
+int m1_layout(tn_plan *p, const std::vector<NetCheck> *chkp) {
+  const size_t as = acc_size(p->dtype);
+  const bool big = p->log2m > kMaxLog2Acc;  // bucket ranges in the scatter
   p->h_tslot.push_back((int32_t)p->h_slots.size());
 
   // Samples per scatter block: as many as fit 64 KB of LDS (two blocks per CU),
@@ -214,6 +247,8 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   // handed out largest first), then a default configuration (one bank, as
   // many samples per item as fit 80 KB of LDS); TN_FLAG_AUTOTUNE may retune.
   if (p->flags & TN_FLAG_PERSISTENT) {
+    if (!chkp) return set_error(TN_ERR_UNSUPPORTED, "persistent kernel: not for this plan");
+    const std::vector<NetCheck> &chk = *chkp;
     if (p->log2m < 6 || p->log2m > 12)
       return set_error(TN_ERR_UNSUPPORTED, "persistent kernel: m = %lld outside 64..4096", (long long)p->m);
     p->fused = true;
@@ -284,6 +319,8 @@ int m1_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   }
   return TN_OK;
 }
+
+namespace {
 
 int m1_tables(tn_plan *p, int64_t c0, int64_t n, hipStream_t st, const int32_t **tables) {
   if (p->d_injected) {
@@ -371,8 +408,9 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
                                  (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, p->d_cbuf,
                                  p->d_partial, est, st);
     else
-      rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->dtype, p->d_ybuf, (int64_t)p->h_slots.size(), n,
-                             c0, p->S, p->log2m, p->d_tw, est, st);
+      rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_cbeg ? p->d_cbeg : p->d_tslot,
+                             p->d_cbeg ? p->d_cend : p->d_tslot + 1, p->dtype, p->d_ybuf,
+                             (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, est, st);
     if (rc != TN_OK) return rc;
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
   }
@@ -401,6 +439,10 @@ static std::mutex g_tuned_mu;
 
 int m1_autotune(tn_plan *p, hipStream_t st) {
   if (p->log2m > kMaxLog2Acc) return TN_OK;  // bucket ranges: one schedule only
+  if (p->partial) {  // the timing launches read the sub-tensors
+    int rc = partial_prepare(p, st);
+    if (rc != TN_OK) return rc;
+  }
   int64_t entries = 0;
   for (const ScatterSlot &sl : p->h_slots) entries += (int64_t)sl.rows * sl.L;
   const TuneKey key{(int64_t)p->h_slots.size(), entries, p->m, p->S, p->W, p->dtype, p->device, p->fused};
@@ -520,7 +562,9 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
 }
 
 int run_all(tn_plan *p, hipStream_t st, double *stats, double *est) {
-  int rc = (p->method == TN_CYCLIC) ? m1_run(p, st, est) : m2_estimate(p, st, est);
+  int rc = p->partial ? partial_prepare(p, st) : TN_OK;
+  if (rc != TN_OK) return rc;
+  rc = (p->method == TN_CYCLIC) ? m1_run(p, st, est) : m2_estimate(p, st, est);
   if (rc != TN_OK) return rc;
   hipEvent_t ev = nullptr;
   if ((rc = prof_begin(p, st, &ev, TN_KERNEL_STATS)) != TN_OK) return rc;
@@ -616,19 +660,31 @@ int plan_build(tn_plan *p, const tn_network *nets, int n_nets, int method, int64
     return set_error(TN_ERR_UNSUPPORTED, "acyclic method: m = %lld outside [2, 65536]", (long long)m);
   if (n_nets > 65535 && method == TN_CYCLIC)
     return set_error(TN_ERR_UNSUPPORTED, "at most 65535 networks per plan");
+  int rc = plan_common(p);
+  if (rc != TN_OK) return rc;
+  rc = (method == TN_CYCLIC) ? m1_build(p, nets, chk) : m2_build(p, nets, chk);
+  if (rc == TN_OK) rc = plan_alloc_tail(p);
+  if (rc != TN_OK) plan_release(p);
+  return rc;
+}
+
+// Device and its LDS limit.
+int plan_common(tn_plan *p) {
   TN_HIP_CHECK(hipGetDevice(&p->device));
   int lds = 0;
   TN_HIP_CHECK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device));
   p->max_lds = (size_t)lds;
-  int rc = (method == TN_CYCLIC) ? m1_build(p, nets, chk) : m2_build(p, nets, chk);
-  if (rc != TN_OK) {
-    plan_release(p);
-    return rc;
-  }
+  return TN_OK;
+}
+
+// Buffers every plan has: per-sample estimates and the device pointer table
+// of its (virtual) tensors.
+int plan_alloc_tail(tn_plan *p) {
   p->max_stream = 0;
   for (const StreamDesc &sd : p->h_streams) p->max_stream = std::max<int64_t>(p->max_stream, (int64_t)sd.n);
-  if ((rc = dev_alloc(&p->d_est, (size_t)n_nets * (size_t)S)) != TN_OK) { plan_release(p); return rc; }
-  if ((rc = dev_alloc(&p->d_data, (size_t)p->n_tensors)) != TN_OK) { plan_release(p); return rc; }
+  int rc;
+  if ((rc = dev_alloc(&p->d_est, (size_t)p->n_nets * (size_t)p->S)) != TN_OK) return rc;
+  if ((rc = dev_alloc(&p->d_data, (size_t)p->n_tensors)) != TN_OK) return rc;
   p->bound.assign((size_t)p->n_tensors, nullptr);
   TN_HIP_CHECK(hipMemset(p->d_data, 0, (size_t)p->n_tensors * sizeof(void *)));
   TN_HIP_CHECK(hipDeviceSynchronize());
@@ -636,6 +692,7 @@ int plan_build(tn_plan *p, const tn_network *nets, int n_nets, int method, int64
 }
 
 int plan_bind(tn_plan *p, const tn_network *nets, hipStream_t st) {
+  if (p->partial) return partial_bind(p, nets, st);
   bool changed = false;
   for (int j = 0; j < p->n_nets; ++j) {
     const tn_network &n = nets[j];
@@ -722,6 +779,7 @@ void plan_release(tn_plan *p) {
   p->graph_exec = nullptr;
   p->graph = nullptr;
   if (p->m2) m2_release(p);
+  if (p->partial) partial_release(p);
   void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data,    p->d_modes,
                   p->d_slots,   p->d_tslot,  p->d_nets,     p->d_tw,      p->d_ybuf,
                   p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn, p->d_cbuf, p->d_partial,
@@ -758,6 +816,8 @@ int64_t plan_query(const tn_plan *p, int key) {
     case 9: return p->fused ? p->fused_chunk : p->chunk;
     case 10: return p->method == TN_CYCLIC ? (p->fused ? p->fused_banks : p->banks) : 0;
     case 11: return p->fused ? 1 : 0;
+    case 12: return p->partial ? p->n_out : p->n_nets;
+    case 13: return p->partial ? p->n_free : 0;
     default: return set_error(TN_ERR_ARG, "unknown query key %d", key);
   }
 }
@@ -811,6 +871,7 @@ int plan_get_sketches(tn_plan *p, const tn_network *nets, int64_t first, int64_t
   int rc = plan_bind(p, nets, st);
   if (rc != TN_OK) return rc;
   if (p->method == TN_ACYCLIC) return m2_get_sketches(p, first, count, st, out);
+  if (p->partial && (rc = partial_prepare(p, st)) != TN_OK) return rc;
   for (int64_t c0 = first; c0 < first + count; c0 += p->chunk) {
     const int64_t n = std::min(p->chunk, first + count - c0);
     const int32_t *tables = nullptr;

@@ -147,7 +147,9 @@ int launch_hashgen(const StreamDesc *streams, int64_t n_streams, int64_t W, int6
 
 int launch_m1_scatter(const M1Launch &L, hipStream_t st);
 
-int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tensor_slot_begin,
+// Network j's tensors are the entries [nets[j].t0, nets[j].t1) of tbeg/tend:
+// entry k's sketch sums the slots [tbeg[k], tend[k]).
+int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend,
                       int dtype, const void *ybuf, int64_t n_slots, int64_t samples,
                       int64_t sample0, int64_t S, int log2m, const void *twiddles,
                       double *est, hipStream_t st);

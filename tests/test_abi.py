@@ -71,7 +71,7 @@ def test_argument_codes(T):
         T.tn_sketch_plan([s], 3, 16, 4, 0)
     assert ei.value.code == T.TN_ERR_ARG
     with pytest.raises(T.TNError) as ei:
-        T.tn_sketch_plan([s], 1, 16, 4, 0, flags=0x80)
+        T.tn_sketch_plan([s], 1, 16, 4, 0, flags=0x40000000)
     assert ei.value.code == T.TN_ERR_ARG
     big = W.Network([1, 1], [1 << 21, 1 << 21], [(0, 1)])
     with pytest.raises(T.TNError) as ei:
