@@ -122,6 +122,13 @@ extern "C" {
                                    Example 3).  A negative reference, not an estimator to use
                                    (TN_ERR_UNSUPPORTED with TN_ACYCLIC) */
 
+#define TN_FLAG_RESIDENT 0x80u /* TN_CYCLIC only, not with TN_FLAG_PERSISTENT: keep the time-domain
+                                   sketches of all S samples (and their hash tables) in device
+                                   memory (S <= 65535 and at most 16 GiB for both, else
+                                   TN_ERR_UNSUPPORTED), so that a stream of updates can change
+                                   them (tn_sketch_update) and estimates can be read at any time
+                                   (tn_sketch_combine) without rescanning the tensors */
+
 /* Kernel kinds for tn_plan_kernel_time. */
 #define TN_KERNEL_HASH 0        /* count-sketch table generation */
 #define TN_KERNEL_SKETCH 1      /* sketching pass: cyclic scatter / acyclic leaf+SMVP sweep */
@@ -199,6 +206,33 @@ int tn_sketch_estimate(tn_plan *plan, const tn_network *nets, void *stream, doub
  * TN_ERR_UNSUPPORTED (an intermediate over 2^31 entries), TN_ERR_OOM, TN_ERR_HIP.
  */
 int tn_contract_exact(const tn_network *net, void *stream, double *out);
+
+/*
+ * Turnstile streaming (TN_FLAG_RESIDENT plans; the general turnstile setting
+ * of Algorithm 1: the sketches x_k are kept, and an update, which may change
+ * any entry by any amount, costs O(q_k) per sample).  A resident plan's
+ * sketches start as those of tn_sketch_estimate's last scan of the bound
+ * tensors, or zero after tn_sketch_reset (then the bound tensors are never
+ * read); updates are linear, so the sketches always equal those of the
+ * tensors the scan (or zero) plus all updates describe.
+ *
+ * tn_sketch_update -- X_k(index[u]) += delta[u], u < n, for tensor `tensor`
+ *   of network `net`, in the sketches of every sample.  index: DEVICE, n int64
+ *   row-major entry indices (entries outside [0, size) are ignored); delta:
+ *   DEVICE, n doubles (added in the sketch precision: FP64 for TN_F64 data,
+ *   FP32 otherwise, with device atomics, so the order of equal-bucket adds,
+ *   and hence the low bits, may vary run to run).  The tensor data is not
+ *   touched.  Asynchronous on `stream`.
+ * tn_sketch_combine -- the estimates of the current sketches: the combine and
+ *   per-network statistics of tn_sketch_estimate, without the scan.  stats /
+ *   samples_out as for tn_sketch_estimate.
+ * tn_sketch_reset -- zero every sketch (all-zero tensors).
+ * TN_ERR_ARG on a plan without TN_FLAG_RESIDENT.
+ */
+int tn_sketch_update(tn_plan *plan, int32_t net, int32_t tensor, int64_t n, const int64_t *index,
+                     const double *delta, void *stream);
+int tn_sketch_combine(tn_plan *plan, void *stream, double *stats, double *samples_out);
+int tn_sketch_reset(tn_plan *plan, void *stream);
 
 /*
  * tn_partial_plan -- partial TNC (Corollary 1) with the estimator of Eq. (1).

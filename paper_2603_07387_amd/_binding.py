@@ -30,6 +30,7 @@ TN_FLAG_MFMA_BF16 = 0x8
 TN_FLAG_PERSISTENT = 0x10
 TN_FLAG_PROFILE_SKETCH = 0x20
 TN_FLAG_PRIOR_XCORR = 0x40
+TN_FLAG_RESIDENT = 0x80
 TN_KERNEL_HASH, TN_KERNEL_SKETCH, TN_KERNEL_COMBINE, TN_KERNEL_STATS = 0, 1, 2, 3
 
 _DTYPES = {torch.float64: TN_F64, torch.float32: TN_F32, torch.bfloat16: TN_BF16}
@@ -98,6 +99,12 @@ def load():
     L.tn_median_of_means.restype = ctypes.c_int
     L.tn_partial_plan.argtypes = [net_p, i64, i64, u64, u32, P(vp)]
     L.tn_partial_plan.restype = ctypes.c_int
+    L.tn_sketch_update.argtypes = [vp, i32, i32, i64, vp, vp, vp]
+    L.tn_sketch_update.restype = ctypes.c_int
+    L.tn_sketch_combine.argtypes = [vp, vp, vp, vp]
+    L.tn_sketch_combine.restype = ctypes.c_int
+    L.tn_sketch_reset.argtypes = [vp, vp]
+    L.tn_sketch_reset.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -468,6 +475,28 @@ class Plan:
             _device_buffer(samples_out, torch.float64, self.n_nets * self.S, "samples_out")
         tn_sketch_estimate(self.handle, self._arr, stream, stats, samples_out)
         return stats
+
+    def update(self, tensor, index, delta, net=0, stream=None):
+        """Turnstile update of a resident plan: X_tensor(index[u]) += delta[u]
+        (index: int64 device tensor of row-major entry indices, delta: float64)."""
+        n = index.numel()
+        _device_buffer(index, torch.int64, n, "index")
+        _device_buffer(delta, torch.float64, n, "delta")
+        _check(load().tn_sketch_update(self.handle, net, tensor, n, _ptr(index), _ptr(delta), _stream(stream)))
+
+    def combine(self, stats=None, samples_out=None, stream=None):
+        """Estimates of a resident plan's current sketches (no scan of the tensors)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if stats is None:
+            stats = torch.empty(2 * self.n_nets, dtype=torch.float64, device=dev)
+        _device_buffer(stats, torch.float64, 2 * self.n_nets, "stats")
+        if samples_out is not None:
+            _device_buffer(samples_out, torch.float64, self.n_nets * self.S, "samples_out")
+        _check(load().tn_sketch_combine(self.handle, _stream(stream), _ptr(stats), _ptr(samples_out)))
+        return stats
+
+    def reset(self, stream=None):
+        _check(load().tn_sketch_reset(self.handle, _stream(stream)))
 
     def hashes(self, first=0, count=None, stream=None):
         count = self.S - first if count is None else count

@@ -125,8 +125,11 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
   if (m < 1 || (m & (m - 1)) != 0) return set_error(TN_ERR_ARG, "m = %lld is not a power of two", (long long)m);
   if (method != TN_CYCLIC && method != TN_ACYCLIC) return set_error(TN_ERR_ARG, "method %d", method);
   if (flags & ~(uint32_t)(TN_FLAG_GRAPH | TN_FLAG_PROFILE | TN_FLAG_AUTOTUNE | TN_FLAG_MFMA_BF16 |
-                          TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH | TN_FLAG_PRIOR_XCORR))
+                          TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH | TN_FLAG_PRIOR_XCORR |
+                          TN_FLAG_RESIDENT))
     return set_error(TN_ERR_ARG, "unknown flags 0x%x", flags);
+  if ((flags & TN_FLAG_RESIDENT) && (method != TN_CYCLIC || (flags & TN_FLAG_PERSISTENT)))
+    return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_RESIDENT applies to the cyclic method's slot kernels");
   if ((flags & TN_FLAG_PRIOR_XCORR) && method != TN_CYCLIC)
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_PRIOR_XCORR applies to the cyclic method");
   if ((flags & TN_FLAG_PROFILE_SKETCH) && !(flags & TN_FLAG_PROFILE))
@@ -200,6 +203,25 @@ int tn_plan_get_sketches(tn_plan *plan, const tn_network *nets, int64_t first, i
   clear_error();
   if (!plan || !nets || !out) return set_error(TN_ERR_ARG, "null plan, networks or out");
   return plan_get_sketches(plan, nets, first, count, (hipStream_t)stream, out);
+}
+
+int tn_sketch_update(tn_plan *plan, int32_t net, int32_t tensor, int64_t n, const int64_t *index,
+                     const double *delta, void *stream) {
+  clear_error();
+  if (!plan) return set_error(TN_ERR_ARG, "null plan");
+  return plan_update(plan, net, tensor, n, index, delta, (hipStream_t)stream);
+}
+
+int tn_sketch_combine(tn_plan *plan, void *stream, double *stats, double *samples_out) {
+  clear_error();
+  if (!plan || !stats) return set_error(TN_ERR_ARG, "null plan or stats");
+  return plan_combine(plan, (hipStream_t)stream, stats, samples_out);
+}
+
+int tn_sketch_reset(tn_plan *plan, void *stream) {
+  clear_error();
+  if (!plan) return set_error(TN_ERR_ARG, "null plan");
+  return plan_reset(plan, (hipStream_t)stream);
 }
 
 int tn_plan_kernel_time(tn_plan *plan, int32_t kind, double *ms, int64_t *launches) {

@@ -85,6 +85,7 @@ struct tn_plan {
   int64_t chunk_alloc = 0;  // samples the workspace was sized for
   size_t worst_cols_rows = 0;
   bool tuned = false;
+  bool tables_ready = false;  // d_tables holds every sample's tables (resident plans)
 
   // persistent fused kernel (TN_FLAG_PERSISTENT)
   bool fused = false;
@@ -166,6 +167,10 @@ int add_tensor_slots(tn_plan *p, int32_t gtensor, int32_t mode0, int q, const in
 int m1_layout(tn_plan *p, const std::vector<NetCheck> *chk);
 int plan_common(tn_plan *p);
 int plan_alloc_tail(tn_plan *p);
+// resident sketches (TN_FLAG_RESIDENT)
+int plan_update(tn_plan *p, int net, int tensor, int64_t n, const int64_t *idx, const double *delta, hipStream_t st);
+int plan_combine(tn_plan *p, hipStream_t st, double *stats, double *samples_out);
+int plan_reset(tn_plan *p, hipStream_t st);
 // partial TNC (partial.hip)
 int partial_build(tn_plan *p, const tn_network *net);
 int partial_bind(tn_plan *p, const tn_network *nets, hipStream_t st);

@@ -19,6 +19,7 @@ namespace {
 
 constexpr int kMaxRowsPerSlot = 2048;
 constexpr size_t kWorkspaceBudget = (size_t)1 << 30;  // tables + sketches per pass
+constexpr size_t kResidentBudget = (size_t)16 << 30;  // all samples' sketches and tables (TN_FLAG_RESIDENT)
 
 template <typename T>
 int dev_alloc(T **ptr, size_t count) {
@@ -238,8 +239,15 @@ int m1_layout(tn_plan *p, const std::vector<NetCheck> *chkp) {
   int64_t chunk = (int64_t)std::max<size_t>(1, kWorkspaceBudget / std::max<size_t>(1, per_sample));
   chunk = std::min<int64_t>(chunk, p->S);
   chunk = std::min<int64_t>(chunk, 65535);
+  if (p->flags & TN_FLAG_RESIDENT) {
+    // every sample's sketches and hash tables stay in device memory
+    if (p->S > 65535 || (double)per_sample * (double)p->S > (double)kResidentBudget)
+      return set_error(TN_ERR_UNSUPPORTED, "resident sketches: %lld samples of %zu bytes exceed the %zu-byte limit",
+                       (long long)p->S, per_sample, kResidentBudget);
+    chunk = p->S;
+  }
   p->chunk_alloc = chunk;
-  if (chunk > 16) chunk = chunk / 16 * 16;  // a multiple of every samples-per-pass choice
+  if (chunk > 16 && !(p->flags & TN_FLAG_RESIDENT)) chunk = chunk / 16 * 16;  // a multiple of every samples-per-pass choice
   p->chunk = chunk;
   int64_t table_samples = chunk;
 
@@ -327,6 +335,7 @@ int m1_tables(tn_plan *p, int64_t c0, int64_t n, hipStream_t st, const int32_t *
     *tables = p->d_injected + c0 * p->W;
     return TN_OK;
   }
+  p->tables_ready = c0 == 0 && n == p->S;  // a resident plan's tables cover every sample
   *tables = p->d_tables;
   hipEvent_t ev = nullptr;
   int rc = prof_begin(p, st, &ev, TN_KERNEL_HASH);
@@ -820,6 +829,55 @@ int64_t plan_query(const tn_plan *p, int key) {
     case 13: return p->partial ? p->n_free : 0;
     default: return set_error(TN_ERR_ARG, "unknown query key %d", key);
   }
+}
+
+// Resident sketches (TN_FLAG_RESIDENT): turnstile updates, the combine alone,
+// and a reset to the sketches of all-zero tensors.
+int resident_check(const tn_plan *p) {
+  if (!(p->flags & TN_FLAG_RESIDENT) || p->method != TN_CYCLIC)
+    return set_error(TN_ERR_ARG, "the plan was not built with TN_FLAG_RESIDENT (cyclic method)");
+  return TN_OK;
+}
+
+int plan_update(tn_plan *p, int net, int tensor, int64_t n, const int64_t *idx, const double *delta, hipStream_t st) {
+  int rc = resident_check(p);
+  if (rc != TN_OK) return rc;
+  if (net < 0 || net >= p->n_nets || tensor < 0 || tensor >= p->net_p[(size_t)net])
+    return set_error(TN_ERR_ARG, "network %d tensor %d is not in the plan", net, tensor);
+  if (n < 0 || (n > 0 && (!idx || !delta))) return set_error(TN_ERR_ARG, "bad update arrays");
+  if (n == 0) return TN_OK;
+  if (!p->d_injected && !p->tables_ready) {
+    const int32_t *t = nullptr;
+    if ((rc = m1_tables(p, 0, p->S, st, &t)) != TN_OK) return rc;
+  }
+  const int32_t *tables = p->d_injected ? p->d_injected : p->d_tables;
+  const size_t g = (size_t)(p->net_tensor0[(size_t)net] + tensor);
+  const int32_t slot0 = p->h_tslot[g];
+  const ScatterSlot &sl = p->h_slots[(size_t)slot0];
+  return launch_stream_update(p->d_modes, sl.mode0, sl.q, p->tensor_size[g], tables, p->W, p->S, p->log2m,
+                              (int64_t)p->h_slots.size(), slot0, p->dtype, p->d_ybuf, n, idx, delta, st);
+}
+
+int plan_combine(tn_plan *p, hipStream_t st, double *stats, double *samples_out) {
+  int rc = resident_check(p);
+  if (rc != TN_OK) return rc;
+  double *est = samples_out ? samples_out : p->d_est;
+  if (p->two_pass)
+    rc = launch_m1_combine_big(p->n_nets, p->d_tslot, p->d_pairs, p->d_pair0, p->n_pairs, p->dtype, p->d_ybuf,
+                               (int64_t)p->h_slots.size(), p->S, 0, p->S, p->log2m, p->d_tw, p->d_cbuf,
+                               p->d_partial, est, st);
+  else
+    rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->d_tslot + 1, p->dtype, p->d_ybuf,
+                           (int64_t)p->h_slots.size(), p->S, 0, p->S, p->log2m, p->d_tw, est, st);
+  if (rc != TN_OK) return rc;
+  return launch_sample_stats(est, p->n_nets, p->S, stats, st);
+}
+
+int plan_reset(tn_plan *p, hipStream_t st) {
+  int rc = resident_check(p);
+  if (rc != TN_OK) return rc;
+  const size_t bytes = (size_t)p->S * p->h_slots.size() * (size_t)p->m * acc_size(p->dtype);
+  return launch_fill_zero(p->d_ybuf, bytes, st);
 }
 
 int plan_get_hashes(tn_plan *p, int64_t first, int64_t count, hipStream_t st, int32_t *out) {

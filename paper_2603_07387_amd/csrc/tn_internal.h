@@ -174,6 +174,14 @@ int launch_sample_stats(const double *est, int64_t n_nets, int64_t S, double *st
 
 int launch_copy_i32(const int32_t *src, int32_t *dst, int64_t n, hipStream_t st);
 
+// Turnstile updates of resident sketches (stream.hip): n updates X_k(idx[u])
+// += delta[u] of the tensor whose modes are modes[mode0 .. mode0 + q) and whose
+// first slot is slot0, applied to the [S][n_slots][m] sketches of every sample.
+int launch_stream_update(const ModeDesc *modes, int mode0, int q, int64_t size, const int32_t *tables, int64_t W,
+                         int64_t S, int log2m, int64_t n_slots, int32_t slot0, int dtype, void *ybuf, int64_t n,
+                         const int64_t *idx, const double *delta, hipStream_t st);
+int launch_fill_zero(void *buf, size_t bytes, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // Exact contraction.
 // ---------------------------------------------------------------------------

@@ -311,3 +311,94 @@ def batch_stats(nets):
         "mean_p": float(np.mean([n.p for n in nets])),
         "mean_t": float(np.mean([n.t for n in nets])),
     }
+
+
+# ----------------------------------------------------------------------------
+# Streams for the turnstile setting and the two applications (join size,
+# triangle counting).  Seeded and synthetic; they hold no estimator arithmetic.
+# ----------------------------------------------------------------------------
+
+class Stream:
+    """A turnstile stream over a network's tensors: update u adds delta[u] to
+    entry index[u] (row-major) of tensor tensor[u].  dense() applies it to
+    zero tensors (the tensors the stream describes)."""
+
+    def __init__(self, net, tensor, index, delta, name=""):
+        self.net = net                      # structure (data unused)
+        self.tensor = np.asarray(tensor, dtype=np.int32)
+        self.index = np.asarray(index, dtype=np.int64)
+        self.delta = np.asarray(delta, dtype=np.float64)
+        self.name = name
+
+    def __len__(self):
+        return len(self.index)
+
+    def dense(self):
+        data = []
+        for k in range(self.net.p):
+            x = np.zeros(int(np.prod(self.net.shape(k))), dtype=np.float64)
+            sel = self.tensor == k
+            np.add.at(x, self.index[sel], self.delta[sel])
+            data.append(x.reshape(self.net.shape(k)))
+        return self.net.with_data(data)
+
+
+def _zipf_keys(rng, n, count, s):
+    """count keys in [0, n) with P(key = i) proportional to (i + 1)^-s,
+    shuffled so popularity does not follow the index."""
+    w = 1.0 / np.arange(1, n + 1, dtype=np.float64) ** s
+    perm = rng.permutation(n)
+    return perm[rng.choice(n, size=count, p=w / w.sum())]
+
+
+def edge_stream(n=1024, edges=32768, triangles=512, deletions=4096, seed=7):
+    """A directed graph as a stream of edge insertions and deletions, fed to
+    the triangle network tr(A A A) (Cor. 3: X_1 = X_2 = X_3 = A, contractions
+    the 0-based form of {(1,6),(2,3),(4,5)}): random edges with Zipf(0.8)
+    endpoints, `triangles` planted directed 3-cycles, then `deletions` of
+    inserted edges (turnstile).  Each edge update is sent to all three tensors.
+    Returns a Stream."""
+    rng = np.random.default_rng([seed, 31])
+    src = _zipf_keys(rng, n, edges, 0.8)
+    dst = _zipf_keys(rng, n, edges, 0.8)
+    keep = src != dst
+    src, dst = list(src[keep]), list(dst[keep])
+    for _ in range(triangles):
+        a, b, c = rng.choice(n, size=3, replace=False)
+        src += [a, b, c]
+        dst += [b, c, a]
+    src, dst = np.array(src, dtype=np.int64), np.array(dst, dtype=np.int64)
+    sign = np.ones(len(src))
+    gone = rng.choice(len(src), size=min(deletions, len(src)), replace=False)
+    src = np.concatenate([src, src[gone]])
+    dst = np.concatenate([dst, dst[gone]])
+    sign = np.concatenate([sign, -np.ones(len(gone))])
+    net = Network([2, 2, 2], [n] * 6, [(0, 5), (1, 2), (3, 4)], name=f"graph{n}")
+    lin = src * n + dst
+    T = len(lin)
+    return Stream(net, np.repeat(np.arange(3), T), np.tile(lin, 3), np.tile(sign, 3), f"edges{n}")
+
+
+def join_stream(kind="chain", n=256, tuples=20000, s=1.1, seed=9):
+    """Relations as a tuple stream for join-size estimation (Cor. 2): each
+    relation is a frequency tensor over its join attributes, and each tuple an
+    update +1 of its entry.  kind 'chain': R1(a) R2(a,b) R3(b,c) R4(c) joined
+    on a, b, c (acyclic); 'cycle': R1(a,b) R2(b,c) R3(c,a) (cyclic).  Join keys
+    are Zipf(s) over domains of size n.  Returns a Stream."""
+    rng = np.random.default_rng([seed, 41])
+    if kind == "chain":
+        net = Network([1, 2, 2, 1], [n] * 6, [(0, 1), (2, 3), (4, 5)], name=f"join_chain{n}")
+        arities = [1, 2, 2, 1]
+    elif kind == "cycle":
+        net = Network([2, 2, 2], [n] * 6, [(1, 2), (3, 4), (5, 0)], name=f"join_cycle{n}")
+        arities = [2, 2, 2]
+    else:
+        raise ValueError(kind)
+    tensor, index = [], []
+    for k, a in enumerate(arities):
+        cols = [_zipf_keys(rng, n, tuples, s) for _ in range(a)]
+        lin = cols[0] if a == 1 else cols[0] * n + cols[1]
+        tensor.append(np.full(tuples, k))
+        index.append(lin)
+    return Stream(net, np.concatenate(tensor), np.concatenate(index), np.ones(tuples * len(arities)),
+                  f"{kind}{n}")
