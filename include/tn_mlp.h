@@ -37,6 +37,9 @@ int tn_mlp_create(int32_t d_in, int32_t hidden, uint64_t seed, tn_mlp **out);
 /* Number of parameters. */
 int64_t tn_mlp_num_params(const tn_mlp *net);
 
+/* Input width and hidden units of a network. */
+int tn_mlp_shape(const tn_mlp *net, int32_t *d_in, int32_t *hidden);
+
 /* Copy the parameter vector to / from HOST memory (n_params floats).  set
  * also clears the Adam moments and step counter. */
 int tn_mlp_get_params(const tn_mlp *net, float *host_out);
@@ -63,6 +66,25 @@ int tn_mlp_train(tn_mlp *net, const float *X, const float *y, int64_t n, int32_t
                  int32_t epochs, float lr, void *stream, double *losses);
 
 void tn_mlp_destroy(tn_mlp *net);
+
+/* Save the parameters (and n_meta <= 64 caller values, e.g. the label mean,
+ * standard deviation and margin of a selector) to a file: the 8 bytes
+ * "TNMLP\0\0\1", then little-endian uint32 version (1), int32 d_in, int32
+ * hidden, int32 n_meta, int64 n_params, n_meta doubles, n_params floats, and
+ * the CRC-32 (ISO 3309 / ITU-T V.42) of every preceding byte. */
+int tn_mlp_save(const tn_mlp *net, const char *path, const double *meta, int32_t n_meta);
+
+/* Load a file written by tn_mlp_save into a new network on the current
+ * device (Adam moments zero); meta receives its n_meta values (max_meta room).
+ * TN_ERR_ARG for a missing file, a wrong magic or version, a size that does
+ * not match the header, or a CRC mismatch. */
+int tn_mlp_load(const char *path, tn_mlp **out, double *meta, int32_t max_meta, int32_t *n_meta);
+
+/* Register the regressor that TN_SIZE_LEARNED sizing uses (tn_sketch_size,
+ * tn_sketch_plan with TN_FLAG_SIZE_LEARNED): it predicts the standardized
+ * label, and log v(m) = prediction * sd + mu + margin.  The network must stay
+ * alive while registered; NULL unregisters.  Process-wide. */
+int tn_set_size_selector(const tn_mlp *net, double mu, double sd, double margin);
 
 #ifdef __cplusplus
 }

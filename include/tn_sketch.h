@@ -129,6 +129,9 @@ extern "C" {
                                    them (tn_sketch_update) and estimates can be read at any time
                                    (tn_sketch_combine) without rescanning the tensors */
 
+#define TN_FLAG_SIZE_PILOT 0x100u   /* m <= 0: size the plan from a pilot (see tn_sketch_size) */
+#define TN_FLAG_SIZE_LEARNED 0x200u /* m <= 0: size the plan from the registered regressor */
+
 /* Kernel kinds for tn_plan_kernel_time. */
 #define TN_KERNEL_HASH 0        /* count-sketch table generation */
 #define TN_KERNEL_SKETCH 1      /* sketching pass: cyclic scatter / acyclic leaf+SMVP sweep */
@@ -152,7 +155,18 @@ typedef struct tn_plan tn_plan;
  *   nets, n_nets : structures (orders, dims, edges, dtype; data may be NULL
  *                  here, it is bound by each tn_sketch_estimate call).
  *   method       : TN_CYCLIC (any network) or TN_ACYCLIC (trees only).
- *   m            : sketch size (the paper's m), a power of two,
+ *   m            : sketch size (the paper's m), a power of two, or m <= 0 to
+ *                  let the plan choose it (and S too when samples <= 0) for
+ *                  the target of tn_set_size_target (default eps = 1e-2,
+ *                  delta = 0.25): the size of least work S (q N + p m log2 m)
+ *                  over the method's ladder (2^6 .. 2^14 cyclic, .. 2^13
+ *                  acyclic) with v_j(m) / S <= delta eps^2 for every network j
+ *                  (Chebyshev on the plain mean), v from TN_FLAG_SIZE_PILOT,
+ *                  TN_FLAG_SIZE_LEARNED or, with neither, the variance bound
+ *                  of Lemma 6 / Lemma 9 (see tn_sketch_size).  Pilot and
+ *                  learned sizing read the tensors (data must be bound here)
+ *                  and synchronize the default stream.  tn_plan_query keys 3
+ *                  and 2 return the chosen m and S.  Otherwise m is
  *                  1 <= m <= 65536 for TN_CYCLIC (above 16384 the scatter
  *                  splits each sketch's buckets over blocks and takes one
  *                  sample per pass; when the m-point FFT does not fit in LDS,
@@ -160,7 +174,8 @@ typedef struct tn_plan tn_plan;
  *                  runs in two passes through a device workspace of
  *                  tensors x m complex values per sample),
  *                  2 <= m <= 8192 for TN_ACYCLIC.
- *   samples      : S >= 1 independent sketch samples per network; sample r
+ *   samples      : S >= 1 independent sketch samples per network (S <= 0
+ *                  only with m <= 0: chosen too); sample r
  *                  uses hash key (seed + j, r, stream) for network j.
  *   root         : TN_ACYCLIC root tensor o (Algorithm 2), same for every
  *                  network; -1 lets the planner pick tensor 0.  Ignored for
@@ -329,6 +344,53 @@ int tn_plan_get_sketches(tn_plan *plan, const tn_network *nets, int64_t first, i
  * kernel was launched on; the call waits for them.
  */
 int tn_plan_kernel_time(tn_plan *plan, int32_t kind, double *ms, int64_t *launches);
+
+/*
+ * Sketch size for a target of Def. 4: P(|y - tc| > eps prod_k ||X_k||_F) <=
+ * delta, following Theorem 1's proof.  One estimate at sketch size m has
+ * variance v(m) prod_k ||X_k||_F^2; the mean of S estimates misses eps with
+ * probability p <= v(m) / (S eps^2) (Chebyshev), and the median of G such
+ * means (G odd) misses only when (G + 1) / 2 of them do, a binomial tail.
+ *   mode TN_SIZE_BOUND   : v(m) from the bounds the theorem uses, 3^t / m
+ *                          (Lemma 6, TN_CYCLIC) or (1 + 8/m)^{2t} - 1 (Lemma 9,
+ *                          TN_ACYCLIC); needs no data;
+ *        TN_SIZE_PILOT   : 16 estimates at m0 = 1024 (one batched plan, seed
+ *                          `seed`), v(m) = v(m0) m0 / m (the 1/m law of Lemmas 2,
+ *                          3 and 6);
+ *        TN_SIZE_LEARNED : the regressor registered with tn_set_size_selector
+ *                          (include/tn_mlp.h) predicts log v(m) from network
+ *                          features (structure, sizes against m, the two bounds,
+ *                          per-tensor data statistics), plus its margin.
+ * For every network the choice over the ladder (2^6 .. 2^14 cyclic, .. 2^13
+ * acyclic) minimizes the work G S (q N + p m log2 m) (q the mean order, N the
+ * entries): with max_groups = 1, G = 1 and p = delta; otherwise p ranges over
+ * 0.02 .. 0.48 and G is the smallest odd count, at most max_groups, with the
+ * tail <= delta.  S <= 2^20; when no m meets the target, the m of least v with
+ * S = 2^20.  out: HOST, n_nets choices.  Pilot and learned modes read the
+ * tensors and synchronize `stream`.
+ */
+#define TN_SIZE_BOUND 0
+#define TN_SIZE_PILOT 1
+#define TN_SIZE_LEARNED 2
+typedef struct tn_size_choice {
+  int64_t m;        /* sketch size */
+  int64_t samples;  /* S: estimates per group */
+  int32_t groups;   /* G: the estimate is the median of G group means (odd; 1 = plain mean) */
+  double p_group;   /* Chebyshev miss probability allowed per group */
+  double v;         /* v(m) = Var(one estimate) / prod_k ||X_k||_F^2 used */
+  double work;      /* G S (q N + p m log2 m) */
+} tn_size_choice;
+int tn_sketch_size(const tn_network *nets, int32_t n_nets, int32_t method, double eps, double delta,
+                   int32_t max_groups, int32_t mode, uint64_t seed, void *stream, tn_size_choice *out);
+
+/* Smallest odd G with P(Bin(G, p_group) >= (G + 1) / 2) <= delta (the median
+ * trick of Theorem 1's proof), 0 < delta < 1, 0 < p_group < 1/2; at most 4095
+ * (else TN_ERR_UNSUPPORTED). */
+int tn_median_groups(double delta, double p_group, int32_t *groups);
+
+/* Target (eps, delta) of plans sized by tn_sketch_plan (m <= 0), process-wide;
+ * defaults eps = 1e-2, delta = 0.25 (with Chebyshev, two standard errors). */
+int tn_set_size_target(double eps, double delta);
 
 /*
  * tn_tensor_stats -- per-tensor statistics used as features by the sketch-size

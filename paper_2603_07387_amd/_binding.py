@@ -31,6 +31,9 @@ TN_FLAG_PERSISTENT = 0x10
 TN_FLAG_PROFILE_SKETCH = 0x20
 TN_FLAG_PRIOR_XCORR = 0x40
 TN_FLAG_RESIDENT = 0x80
+TN_FLAG_SIZE_PILOT = 0x100
+TN_FLAG_SIZE_LEARNED = 0x200
+TN_SIZE_BOUND, TN_SIZE_PILOT, TN_SIZE_LEARNED = 0, 1, 2
 TN_KERNEL_HASH, TN_KERNEL_SKETCH, TN_KERNEL_COMBINE, TN_KERNEL_STATS = 0, 1, 2, 3
 
 _DTYPES = {torch.float64: TN_F64, torch.float32: TN_F32, torch.bfloat16: TN_BF16}
@@ -44,6 +47,17 @@ class TNError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"[{code}] {msg}")
         self.code = code
+
+
+class tn_size_choice(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64),
+        ("samples", ctypes.c_int64),
+        ("groups", ctypes.c_int32),
+        ("p_group", ctypes.c_double),
+        ("v", ctypes.c_double),
+        ("work", ctypes.c_double),
+    ]
 
 
 class tn_network(ctypes.Structure):
@@ -105,6 +119,19 @@ def load():
     L.tn_sketch_combine.restype = ctypes.c_int
     L.tn_sketch_reset.argtypes = [vp, vp]
     L.tn_sketch_reset.restype = ctypes.c_int
+    L.tn_sketch_size.argtypes = [net_p, i32, i32, ctypes.c_double, ctypes.c_double, i32, i32, u64, vp,
+                                 P(tn_size_choice)]
+    L.tn_sketch_size.restype = ctypes.c_int
+    L.tn_median_groups.argtypes = [ctypes.c_double, ctypes.c_double, P(i32)]
+    L.tn_median_groups.restype = ctypes.c_int
+    L.tn_set_size_target.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.tn_set_size_target.restype = ctypes.c_int
+    L.tn_set_size_selector.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.tn_set_size_selector.restype = ctypes.c_int
+    L.tn_mlp_save.argtypes = [vp, ctypes.c_char_p, P(ctypes.c_double), i32]
+    L.tn_mlp_save.restype = ctypes.c_int
+    L.tn_mlp_load.argtypes = [ctypes.c_char_p, P(vp), P(ctypes.c_double), i32, P(i32)]
+    L.tn_mlp_load.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -308,6 +335,41 @@ def tn_tensor_stats_noalloc(specs, stream=None):
     return out.reshape(nt, 4)
 
 
+def tn_sketch_size(specs, method, eps, delta, max_groups=1, mode=TN_SIZE_BOUND, seed=0, stream=None):
+    """Per network a dict(m, samples, groups, p_group, v, work) (tn_sketch_size)."""
+    arr = specs if isinstance(specs, ctypes.Array) else _array(specs)
+    out = (tn_size_choice * len(arr))()
+    _check(load().tn_sketch_size(arr, len(arr), method, eps, delta, max_groups, mode, seed, _stream(stream), out))
+    return [{k: getattr(c, k) for k, _ in tn_size_choice._fields_} for c in out]
+
+
+def tn_median_groups(delta, p_group):
+    g = ctypes.c_int32()
+    _check(load().tn_median_groups(delta, p_group, ctypes.byref(g)))
+    return g.value
+
+
+def tn_set_size_target(eps, delta):
+    _check(load().tn_set_size_target(eps, delta))
+
+
+def tn_set_size_selector(mlp_handle, mu, sd, margin):
+    _check(load().tn_set_size_selector(mlp_handle, mu, sd, margin))
+
+
+def tn_mlp_save(net, path, meta=()):
+    m = (ctypes.c_double * max(1, len(meta)))(*meta)
+    _check(load().tn_mlp_save(net, os.fsencode(path), m, len(meta)))
+
+
+def tn_mlp_load(path, max_meta=64):
+    h = ctypes.c_void_p()
+    m = (ctypes.c_double * max_meta)()
+    n = ctypes.c_int32()
+    _check(load().tn_mlp_load(os.fsencode(path), ctypes.byref(h), m, max_meta, ctypes.byref(n)))
+    return h, list(m[:n.value])
+
+
 def tn_median_of_means(samples, n_nets, S, groups, stream, out):
     return _check(load().tn_median_of_means(_ptr(samples), n_nets, S, groups, _stream(stream), _ptr(out)))
 
@@ -340,6 +402,7 @@ def _mlp_lib():
                                ctypes.c_float, vp, P(ctypes.c_double)]
     L.tn_mlp_destroy.argtypes = [vp]
     L.tn_mlp_destroy.restype = None
+    L.tn_mlp_shape.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32)]
     L._mlp_ready = True
     return L
 
@@ -440,6 +503,20 @@ class MLP:
         self._rows(X, y)
         return tn_mlp_train(self.handle, X, y, batch, epochs, lr, stream)
 
+    def save(self, path, meta=()):
+        tn_mlp_save(self.handle, path, meta)
+
+    @classmethod
+    def load(cls, path):
+        """A network read from a tn_mlp_save file, and the file's meta values."""
+        h, meta = tn_mlp_load(path)
+        obj = cls.__new__(cls)
+        obj.handle = h
+        d, hdn = ctypes.c_int32(), ctypes.c_int32()
+        _check(_mlp_lib().tn_mlp_shape(h, ctypes.byref(d), ctypes.byref(hdn)))
+        obj.d_in, obj.hidden = d.value, hdn.value
+        return obj, meta
+
     def close(self):
         if self.handle is not None and self.handle.value:
             tn_mlp_destroy(self.handle)
@@ -460,8 +537,8 @@ class Plan:
         self._arr = _array(self.specs)   # marshalled once; rebinding data goes through the specs
         self.handle = tn_sketch_plan(self._arr, method, m, samples, seed, root, flags)
         self.n_nets = len(self.specs)
-        self.S = samples
-        self.m = m
+        self.S = self.query(2)      # the chosen values when m <= 0
+        self.m = self.query(3)
 
     def query(self, key):
         return tn_plan_query(self.handle, key)

@@ -121,12 +121,16 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
   if (!out) return set_error(TN_ERR_ARG, "out is null");
   *out = nullptr;
   if (!nets || n_nets < 1) return set_error(TN_ERR_ARG, "need at least one network");
-  if (samples < 1) return set_error(TN_ERR_ARG, "samples = %lld", (long long)samples);
-  if (m < 1 || (m & (m - 1)) != 0) return set_error(TN_ERR_ARG, "m = %lld is not a power of two", (long long)m);
+  if (samples < 1 && m > 0) return set_error(TN_ERR_ARG, "samples = %lld", (long long)samples);
+  if (m > 0 && (m & (m - 1)) != 0) return set_error(TN_ERR_ARG, "m = %lld is not a power of two", (long long)m);
   if (method != TN_CYCLIC && method != TN_ACYCLIC) return set_error(TN_ERR_ARG, "method %d", method);
+  if ((flags & TN_FLAG_SIZE_PILOT) && (flags & TN_FLAG_SIZE_LEARNED))
+    return set_error(TN_ERR_ARG, "TN_FLAG_SIZE_PILOT and TN_FLAG_SIZE_LEARNED exclude each other");
+  if ((flags & (TN_FLAG_SIZE_PILOT | TN_FLAG_SIZE_LEARNED)) && m > 0)
+    return set_error(TN_ERR_ARG, "sizing flags need m <= 0");
   if (flags & ~(uint32_t)(TN_FLAG_GRAPH | TN_FLAG_PROFILE | TN_FLAG_AUTOTUNE | TN_FLAG_MFMA_BF16 |
                           TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH | TN_FLAG_PRIOR_XCORR |
-                          TN_FLAG_RESIDENT))
+                          TN_FLAG_RESIDENT | TN_FLAG_SIZE_PILOT | TN_FLAG_SIZE_LEARNED))
     return set_error(TN_ERR_ARG, "unknown flags 0x%x", flags);
   if ((flags & TN_FLAG_RESIDENT) && (method != TN_CYCLIC || (flags & TN_FLAG_PERSISTENT)))
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_RESIDENT applies to the cyclic method's slot kernels");
@@ -140,9 +144,25 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_MFMA_BF16 applies to the acyclic method");
   if ((flags & TN_FLAG_GRAPH) && (flags & TN_FLAG_PROFILE))
     return set_error(TN_ERR_ARG, "TN_FLAG_PROFILE cannot be combined with TN_FLAG_GRAPH");
+  if (m <= 0) {
+    // validate before any device work, then choose (m, S)
+    for (int j = 0; j < n_nets; ++j) {
+      NetCheck c;
+      int rc = validate_network(&nets[j], j, &c);
+      if (rc == TN_OK && method == TN_ACYCLIC) rc = validate_tree(&nets[j], j, c);
+      if (rc != TN_OK) return rc;
+    }
+    int64_t am = 0, aS = 0;
+    const int rc = auto_size(nets, n_nets, method, flags, seed, samples, &am, &aS);
+    if (rc != TN_OK) return rc;
+    m = am;
+    samples = aS;
+    clear_error();
+  }
   std::unique_ptr<tn_plan> plan(new (std::nothrow) tn_plan());
   if (!plan) return set_error(TN_ERR_OOM, "host allocation");
-  int rc = plan_build(plan.get(), nets, n_nets, method, m, samples, seed, root, flags);
+  int rc = plan_build(plan.get(), nets, n_nets, method, m, samples, seed, root,
+                      flags & ~(uint32_t)(TN_FLAG_SIZE_PILOT | TN_FLAG_SIZE_LEARNED));
   if (rc != TN_OK) return rc;
   *out = plan.release();
   return TN_OK;

@@ -291,6 +291,14 @@ int64_t tn_mlp_num_params(const tn_mlp *net) {
   return net->P;
 }
 
+int tn_mlp_shape(const tn_mlp *net, int32_t *d_in, int32_t *hidden) {
+  clear_error();
+  if (!net || !d_in || !hidden) return set_error(TN_ERR_ARG, "null argument");
+  *d_in = net->D;
+  *hidden = net->H;
+  return TN_OK;
+}
+
 int tn_mlp_get_params(const tn_mlp *net, float *host_out) {
   clear_error();
   if (!net || !host_out) return set_error(TN_ERR_ARG, "null argument");

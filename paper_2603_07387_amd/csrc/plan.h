@@ -171,6 +171,9 @@ int plan_alloc_tail(tn_plan *p);
 int plan_update(tn_plan *p, int net, int tensor, int64_t n, const int64_t *idx, const double *delta, hipStream_t st);
 int plan_combine(tn_plan *p, hipStream_t st, double *stats, double *samples_out);
 int plan_reset(tn_plan *p, hipStream_t st);
+// automatic sketch size of tn_sketch_plan (sizing.hip)
+int auto_size(const tn_network *nets, int n_nets, int method, uint32_t flags, uint64_t seed, int64_t samples,
+              int64_t *m_out, int64_t *S_out);
 // partial TNC (partial.hip)
 int partial_build(tn_plan *p, const tn_network *net);
 int partial_bind(tn_plan *p, const tn_network *nets, hipStream_t st);

@@ -304,7 +304,9 @@ def dataset(measured):
 
 def choose(net, method, logv, eps=1e-2, z=2.0, max_samples=1 << 20, st=None):
     """(m, S, work) minimizing S * work_per_sample subject to
-    z sqrt(v(m)/S) <= eps and S <= max_samples; logv maps m -> log v(m).  When
+    z sqrt(v(m)/S) <= eps and S <= max_samples; logv maps m -> log v(m).  By
+    Chebyshev the miss probability is then at most 1/z^2: this is the
+    library's tn_sketch_size rule with delta = 1/z^2 and one group.  When
     no m of the ladder meets the target within max_samples, the m of least
     predicted v(m) with S = max_samples."""
     st = st or _structure(net)
@@ -373,18 +375,25 @@ class Selector:
         return choose(net, method, self.logv(net, stats, method, st), eps, z, st=st)
 
     def save(self, path):
-        np.savez(path, params=self.mlp.params(), mu=self.mu, sd=self.sd, margin=self.margin,
-                 hidden=self.hidden, d_in=D_IN)
+        """The library's regressor file (tn_mlp_save: header, parameters, CRC)
+        with (mu, sd, margin) as its meta values."""
+        self.mlp.save(path, [self.mu, self.sd, self.margin])
 
     @classmethod
     def load(cls, path):
-        z = np.load(path)
-        if int(z["d_in"]) != D_IN:
-            raise ValueError("feature width differs")
-        sel = cls(int(z["hidden"]))
-        sel.mlp.set_params(z["params"])
-        sel.mu, sel.sd, sel.margin = float(z["mu"]), float(z["sd"]), float(z["margin"])
+        mlp, meta = B.MLP.load(path)
+        if mlp.d_in != D_IN or len(meta) != 3:
+            raise ValueError("not a selector file of this feature width")
+        sel = cls.__new__(cls)
+        sel.mlp, sel.hidden = mlp, mlp.hidden
+        sel.mu, sel.sd, sel.margin = meta
         return sel
+
+    def register(self):
+        """Make this selector the one the library's learned sizing uses
+        (tn_sketch_size with TN_SIZE_LEARNED, tn_sketch_plan with
+        TN_FLAG_SIZE_LEARNED)."""
+        B.tn_set_size_selector(self.mlp.handle, self.mu, self.sd, self.margin)
 
 
 def pilot_choose(specs, net, method, norm, eps=1e-2, z=2.0, m0=1024, S0=16, seed=0):

@@ -60,10 +60,16 @@ def test_validation_codes(T, net, method, code):
 def test_argument_codes(T):
     net = W.triangle(4)
     s = _spec(T, net, "float64")
-    for m in (0, 3, 100):
+    for m in (3, 100):          # m <= 0 asks the plan to choose m (tested on the GPU)
         with pytest.raises(T.TNError) as ei:
             T.tn_sketch_plan([s], 1, m, 4, 0)
         assert ei.value.code == T.TN_ERR_ARG
+    with pytest.raises(T.TNError) as ei:  # sizing flags only with m <= 0, and not both
+        T.tn_sketch_plan([s], 1, 16, 4, 0, flags=T.TN_FLAG_SIZE_PILOT)
+    assert ei.value.code == T.TN_ERR_ARG
+    with pytest.raises(T.TNError) as ei:
+        T.tn_sketch_plan([s], 1, 0, 4, 0, flags=T.TN_FLAG_SIZE_PILOT | T.TN_FLAG_SIZE_LEARNED)
+    assert ei.value.code == T.TN_ERR_ARG
     with pytest.raises(T.TNError) as ei:
         T.tn_sketch_plan([s], 1, 16, 0, 0)
     assert ei.value.code == T.TN_ERR_ARG

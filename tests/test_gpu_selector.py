@@ -84,3 +84,52 @@ def test_learned_beats_pilot(trained):
     assert sb["work_learned"] < sb["work_pilot"]
     # over everything held out: a higher hit rate
     assert sa["hit_rate_learned"] >= sa["hit_rate_pilot"]
+
+
+def test_bound_driven_sizing_against_learned(trained):
+    """Theorem 1's (eps, delta) sizing from the variance bounds (Lemma 6:
+    3^t / m; Lemma 9: (1 + 8/m)^{2t} - 1) with the median of G group means,
+    against the learned choice at the same target (eps = 1e-2, delta = 0.1;
+    the learned size takes the plain mean, Chebyshev at delta on its predicted
+    variance).  Held-out rings, caterpillars and random cyclic networks whose
+    bound-driven sample count stays within 2^21 (on tori it does not: 3^18 /
+    m already needs 10^5 samples per group); each choice runs with fresh seeds
+    and is judged against the exact contraction.  The bound is a guarantee and
+    pays for it: it must hit at least 1 - delta of the networks, and it costs
+    more work than the learned choice, which must still hit 0.8."""
+    import torch
+    import paper_2603_07387_amd as T
+    from paper_2603_07387_amd import selector as S
+    sel = trained[0]
+    sel.register()
+    eps, delta = 1e-2, 0.1
+    pairs = [(n, m) for (n, m) in S.family_networks(120, 47, held_out=True) if "torus" not in n.name][:40]
+    rows = []
+    for i, (net, method) in enumerate(pairs):
+        spec = S._specs([net])
+        try:
+            exact = T.tn_contract_exact(spec[0])
+        except T.TNError:
+            continue
+        meth = T.TN_CYCLIC if method == "cyclic" else T.TN_ACYCLIC
+        norm = float(np.sqrt(np.prod(S.stats_of(spec)[0][:, 1])))
+        b = T.tn_sketch_size(spec, meth, eps, delta, max_groups=1001, mode=T.TN_SIZE_BOUND)[0]
+        if b["samples"] >= 1 << 20 or b["groups"] * b["samples"] > 1 << 21:
+            continue
+        l = T.tn_sketch_size(spec, meth, eps, delta, mode=T.TN_SIZE_LEARNED)[0]
+        tot = b["groups"] * b["samples"]
+        plan = T.Plan(spec, meth, b["m"], tot, 7000 + i)
+        smp = torch.empty(tot, dtype=torch.float64, device="cuda")
+        plan.estimate(samples_out=smp)
+        est_b = float(T.median_of_means(smp.view(1, tot), b["groups"]).cpu()[0])
+        est_l = S.run_estimates(spec, method, l["m"], l["samples"], 9000 + i)[0, 0]
+        rows.append((abs(est_b - exact) / norm <= eps, b["work"], abs(est_l - exact) / norm <= eps, l["work"]))
+    rows = np.array(rows, dtype=np.float64)
+    hit_b, work_b, hit_l, work_l = rows[:, 0].mean(), rows[:, 1].sum(), rows[:, 2].mean(), rows[:, 3].sum()
+    print(f"bound-driven: {len(rows)} networks, hit rate {hit_b:.3f}, work {work_b:.3g}; "
+          f"learned: hit rate {hit_l:.3f}, work {work_l:.3g}; work ratio {work_b / work_l:.1f}")
+    assert len(rows) >= 20
+    assert hit_b >= 1 - delta
+    assert hit_l >= 0.8
+    assert work_b > work_l
+    T.tn_set_size_selector(None, 0.0, 1.0, 0.0)
