@@ -80,7 +80,9 @@ def lib():
         L.orc_m2_estimate.argtypes = net + [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
                                             ctypes.c_int, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_uint64), i64p, i64p,
-                                            dp, dp, dp]
+                                            ctypes.c_int, dp, dp, dp]
+        L.orc_bf16_round.restype = ctypes.c_double
+        L.orc_bf16_round.argtypes = [ctypes.c_double]
         L.orc_dft.argtypes = [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int]
         L.orc_fft.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int]
         L.orc_circ_conv.argtypes = [ctypes.c_int64, dp, dp, dp]
@@ -245,10 +247,12 @@ def xcorr_enumerate(net, m):
     return float(mean[0]), float(var[0]), int(cnt.value)
 
 
-def m2_estimate(net, m, seed, sample, root=0, want_trace=False, tables=None):
+def m2_estimate(net, m, seed, sample, root=0, want_trace=False, tables=None, bf16_products=False):
     """One Method-2 estimate (Algorithm 2).  With want_trace, also the sketch
     x_l of every tensor (x_o for the root) and r_o.  ``tables`` maps stream id ->
-    (h, s) arrays that replace the hash family for that stream."""
+    (h, s) arrays that replace the hash family for that stream.  bf16_products:
+    the BF16-product variant (both factors of every SMVP product and of the
+    root's dot product rounded to BF16, ties to even, via FP32; sums in FP64)."""
     n = _Net(net)
     est = np.zeros(1)
     tr = np.zeros(net.p * m) if want_trace else None
@@ -261,7 +265,7 @@ def m2_estimate(net, m, seed, sample, root=0, want_trace=False, tables=None):
     tab = np.ascontiguousarray(tab, dtype=np.int64)
     rc = lib().orc_m2_estimate(*n.args(), m, seed, sample, root, len(tables), ids,
                                lens.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                               tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(est),
+                               tab.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(bf16_products), _dptr(est),
                                _dptr(tr) if tr is not None else None,
                                _dptr(ro) if ro is not None else None)
     _check(rc, "m2_estimate")
@@ -349,6 +353,11 @@ def circ_conv(x, y):
     out = np.zeros(len(x))
     lib().orc_circ_conv(len(x), _dptr(x), _dptr(y), _dptr(out))
     return out
+
+
+def bf16_round(x):
+    """Nearest BF16 value of x (ties to even), through FP32."""
+    return float(lib().orc_bf16_round(float(x)))
 
 
 def circ_xcorr(x, y):

@@ -595,7 +595,27 @@ typedef struct {
   int64_t **ph; int32_t **ps;                 /* per tensor: pad slots, value at index 0 */
   /* Optional injected tables: stream ids, lengths, and [h..., s...] blocks. */
   int nover; const uint64_t *over_ids; const int64_t *over_len; const int64_t *over_tab;
+  /* BF16-product variant: every product X(i) * (sigma z[b]) of the SMVP of a
+   * tensor with children, and of the root's x_o^T r_o, takes both factors
+   * rounded to BF16 (orc_bf16_round); sums stay FP64. */
+  int bf16;
 } m2_t;
+
+/*
+ * Round to the nearest BF16 value (ties to even), through FP32 first: the
+ * operand rounding of the acyclic method's BF16-product variant (a double is
+ * rounded to the nearest float, that float's low 16 bits to the nearest even
+ * upper half).  Not used by the paper's estimators themselves.
+ */
+double orc_bf16_round(double x) {
+  float f = (float)x;
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (double)f;   /* inf / nan: unchanged */
+  u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
 
 /* Draw one stream's count sketch, or copy it from the injected tables. */
 static void m2_stream(const m2_t *M, uint64_t stream, int64_t n, int64_t *h, int32_t *s) {
@@ -795,7 +815,10 @@ static void smvp(const m2_t *M, int k, const double *z, double *y) {
       recursive_sketch_hash(M, k, cidx, &sg, &b);
       zb = z[b];
     }
-    y[j] += N->data[k][lin] * zb * (double)sg * (double)M->es[e][i1];
+    if (M->bf16 && c > 0)
+      y[j] += orc_bf16_round(N->data[k][lin]) * orc_bf16_round(zb * (double)sg) * (double)M->es[e][i1];
+    else
+      y[j] += N->data[k][lin] * zb * (double)sg * (double)M->es[e][i1];
     ++lin;
   } while (odometer(idx, dims, q));
 }
@@ -851,7 +874,7 @@ static void m2_free(m2_t *M) {
 int orc_m2_estimate(int p, const int *order, const int64_t *dims, const double *const *data,
                     int t, const int *edges, int64_t m, uint64_t seed, uint64_t sample,
                     int root, int nover, const uint64_t *over_ids, const int64_t *over_len,
-                    const int64_t *over_tab, double *est, double *trace, double *rtrace) {
+                    const int64_t *over_tab, int bf16, double *est, double *trace, double *rtrace) {
   net_t N;
   if (m < 1 || net_init(&N, p, order, dims, data, t, edges)) return -1;
   if (root < 0 || root >= p) return -1;
@@ -859,6 +882,7 @@ int orc_m2_estimate(int p, const int *order, const int64_t *dims, const double *
   memset(&M, 0, sizeof(M));
   M.N = &N; M.m = m; M.seed = seed; M.sample = sample; M.root = root;
   M.nover = nover; M.over_ids = over_ids; M.over_len = over_len; M.over_tab = over_tab;
+  M.bf16 = bf16;
   int rc = m2_orient(&M);
   if (rc) { m2_free(&M); return rc; }
   if (N.order[root] == 0) { m2_free(&M); return -1; }
@@ -902,7 +926,23 @@ int orc_m2_estimate(int p, const int *order, const int64_t *dims, const double *
   double *ro = malloc((size_t)m * sizeof(double));
   neighbors_sketch(&M, root, ro, trace);
   double y = 0.0;
-  for (int64_t b = 0; b < m; ++b) y += xo[b] * ro[b];
+  if (!bf16) {
+    for (int64_t b = 0; b < m; ++b) y += xo[b] * ro[b];
+  } else {
+    /* the same sum, sum_i X_o(i) sigma(i) r_o[b(i)], with both factors of each
+     * product rounded to BF16 */
+    int q = N.order[root];
+    const int64_t *rd = N.dims + N.off[root];
+    int64_t idx[64] = {0}, cidx[64];
+    int64_t lin = 0;
+    do {
+      for (int cc = 0; cc < M.nchild[root]; ++cc) cidx[cc] = idx[M.child_mode[root][cc] - N.off[root]];
+      int sg; int64_t b;
+      recursive_sketch_hash(&M, root, cidx, &sg, &b);
+      y += orc_bf16_round(N.data[root][lin]) * orc_bf16_round((double)sg * ro[b]);
+      ++lin;
+    } while (odometer(idx, rd, q));
+  }
   *est = y;
   if (trace) memcpy(trace + (int64_t)root * m, xo, (size_t)m * sizeof(double));
   if (rtrace) memcpy(rtrace, ro, (size_t)m * sizeof(double));

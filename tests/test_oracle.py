@@ -407,3 +407,37 @@ def test_m2_single_edge_is_count_sketch_inner_product(orc):
         h, sg = orc.hash_table(2, s, 0, 30, 16)
         ref = _cs(h, sg, x, 16) @ _cs(h, sg, y, 16)
         assert orc.m2_estimate(net, 16, 2, s)["estimate"] == pytest.approx(ref, rel=1e-12)
+
+
+def test_bf16_rounding_matches_torch(orc):
+    """The oracle's BF16 operand rounding (ties to even, through FP32) against
+    torch's CPU conversion, on random values, exact ties, and values that
+    round differently from FP64 straight to BF16."""
+    import torch
+    rng = np.random.default_rng(3)
+    xs = list(rng.standard_normal(2000) * 10.0 ** rng.integers(-20, 20, 2000))
+    xs += [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -(1.0 + 2.0 ** -8), 2.0 ** -130, 0.0, -0.0, 3.0e38]
+    xs += [1.0 + 2.0 ** -8 + 2.0 ** -40]          # above the tie in FP64, a tie once rounded to FP32
+    ref = torch.tensor(xs, dtype=torch.float64).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([orc.bf16_round(x) for x in xs])
+    assert np.array_equal(got, ref)
+
+
+def test_bf16_products_exact_on_small_integers(orc):
+    """With integer entries small enough that every operand of every product
+    (entries and sketch values) is a BF16 integer, the BF16-product variant of
+    Method 2 equals the FP64 estimator up to the FP64 rounding of the
+    latter's FFT-form tensor sketches (which the BF16 rounding removes)."""
+    tree = W.example5(n=3, seed=2, dist="int")
+    for r in range(4):
+        a = orc.m2_estimate(tree, 16, 5, r, want_trace=True)
+        b = orc.m2_estimate(tree, 16, 5, r, bf16_products=True)["estimate"]
+        assert np.abs(a["r_root"]).max() <= 512 and np.allclose(a["r_root"], np.round(a["r_root"]), atol=1e-9)
+        assert b == pytest.approx(a["estimate"], rel=1e-12, abs=1e-9)
+        assert b == round(b)
+    # and on Gaussian data it differs, by about BF16's rounding of the operands
+    g = W.example5(n=4, seed=3)
+    a = orc.m2_estimate(g, 64, 1, 0, want_trace=True)
+    b = orc.m2_estimate(g, 64, 1, 0, want_trace=True, bf16_products=True)
+    scale = np.linalg.norm(a["x"][0]) * np.linalg.norm(a["r_root"])
+    assert 0 < abs(a["estimate"] - b["estimate"]) <= 2 * 2.0 ** -8 * scale
