@@ -157,7 +157,9 @@ def test_caterpillar_bench_schedule(T, orc, flags):
     in one plan (column-split products, the gathers summing the partials, four
     samples per gather block, the two-child gather kernel); sampled estimates,
     including the last sample of a block and of the plan, against the oracle
-    (FP32 bar, or the BF16 products' bar of levels * 2^-7)."""
+    (FP32 bar, or with BF16 products the per-level bars of test_gpu_m2_bf16:
+    every sketch against exact arithmetic, depth-1 sketches against the
+    BF16-product oracle)."""
     net = W.tt_caterpillar()
     if flags == "fp64":
         plan, views = make_plan(T, [net], "float32", 4096, 4096, 0)
@@ -172,10 +174,21 @@ def test_caterpillar_bench_schedule(T, orc, flags):
     plan.estimate(samples_out=samples)
     torch.cuda.synchronize()
     got = samples.cpu().numpy()
+    from test_gpu_m2_bf16 import bar, subtree_levels
+    d = subtree_levels(net)
     for r in (0, 3, 2047, 4095):
         o = orc.m2_estimate(view, 4096, 0, r, root=0, want_trace=True)
+        b = orc.m2_estimate(view, 4096, 0, r, root=0, want_trace=True, bf16_products=True)
+        sk = plan.sketches(first=r, count=1).cpu().numpy()[0]
+        for l in range(1, net.p):
+            if d[l] == 0:
+                continue
+            nx = np.linalg.norm(o["x"][l])
+            assert np.linalg.norm(sk[l] - o["x"][l]) <= bar(d[l]) * nx, (r, l)
+            if d[l] == 1:
+                assert np.linalg.norm(sk[l] - b["x"][l]) <= 6e-4 * nx, (r, l)
         scale = np.linalg.norm(o["x"][0]) * np.linalg.norm(o["r_root"])
-        assert abs(got[r] - o["estimate"]) <= 31 * 2.0 ** -7 * scale, r
+        assert abs(got[r] - o["estimate"]) <= bar(max(d.values())) * scale, r
 
 
 def test_injective_hashes_exact(T, orc):
