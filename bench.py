@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--batch", type=int, default=None)
     ap.add_argument("--products", default="fp64", choices=["fp64", "bf16"],
                     help="acyclic method: SMVP products on the FP64 (default) or BF16 matrix cores")
+    ap.add_argument("--dft", default="fft", choices=["fft", "bf16"],
+                    help="cyclic method, m = 1024: the combine's DFTs as an LDS FFT (default) or as "
+                         "32 x 32 products on the BF16 matrix cores (TN_FLAG_DFT_BF16)")
     ap.add_argument("--persistent", action="store_true",
                     help="cyclic method: the persistent fused kernel (TN_FLAG_PERSISTENT)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -286,6 +289,9 @@ def main():
     bf16_products = a.products == "bf16" and method == "acyclic"
     if bf16_products:
         flags |= T.TN_FLAG_MFMA_BF16
+    dft_bf16 = a.dft == "bf16" and method == "cyclic"
+    if dft_bf16:
+        flags |= T.TN_FLAG_DFT_BF16
     persistent = a.persistent and method == "cyclic"
     if persistent:
         flags |= T.TN_FLAG_PERSISTENT
@@ -377,6 +383,7 @@ def main():
         "config": {"workload": name, "method": method, "networks": len(nets),
                    "samples_per_network": S, "m": m, "entries": entries,
                    **({"products": "bf16 matrix cores, fp32 accumulation"} if bf16_products else {}),
+                   **({"dft": "bf16 matrix cores (32 x 32 four-step), fp32 accumulation"} if dft_bf16 else {}),
                    "bytes_resident": entries * esize},
         "roofline": roof,
         "at_1e-2": {"median_input_relative_std": float(np.median(rel_std)),

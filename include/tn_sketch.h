@@ -129,6 +129,17 @@ extern "C" {
                                    them (tn_sketch_update) and estimates can be read at any time
                                    (tn_sketch_combine) without rescanning the tensors */
 
+#define TN_FLAG_DFT_BF16 0x400u /* TN_CYCLIC, m = 1024, FP32 or BF16 data, not with TN_FLAG_PERSISTENT:
+                                   the combine takes each 1024-point DFT (Lemma 1's F y_k) as
+                                   32 x 32 dense products on the BF16 matrix cores (four-step:
+                                   32-point DFTs, twiddles, 32-point DFTs), operands rounded to
+                                   BF16, FP32 accumulation, the product over tensors and the
+                                   sum in FP64.  Each of the two stages rounds both factors of
+                                   complex products whose magnitudes sum to at most
+                                   sum_b |y_k[b]| <= U_k = sum |X_k|, so a spectrum value moves
+                                   by at most about 6 2^-9 U_k to first order, and an estimate
+                                   by at most 8 2^-9 (1/m) sum_j sum_k U_k prod_{k' != k}
+                                   |Y_k'[j]| (the tests state the measured error) */
 #define TN_FLAG_SIZE_PILOT 0x100u   /* m <= 0: size the plan from a pilot (see tn_sketch_size) */
 #define TN_FLAG_SIZE_LEARNED 0x200u /* m <= 0: size the plan from the registered regressor */
 
