@@ -19,6 +19,12 @@ Workloads (all inputs seeded and synthetic):
             physical legs contracted against vectors), FP32 N(0,1/64), acyclic
             estimator, m = 4096, S = 4096 samples.
   triangle  three 64 x 64 FP64 N(0,1) matrices, tr(ABC), m = 256.
+  ladder    the literal inner product of two such tensor trains (a cyclic
+            ladder of 64 cores, 94 contractions), cyclic estimator,
+            m = 4096, S = 64.
+Single-network workloads (ttcat, ladder) also report the output-relative
+error against the exact FP64 contraction (tn_contract_exact): their
+input-relative scale prod ||X_k||_F dwarfs the value itself.
 """
 from __future__ import annotations
 
@@ -45,7 +51,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="batched", choices=["torus", "batched", "ttcat", "triangle"])
+    ap.add_argument("--workload", default="batched", choices=["torus", "batched", "ttcat", "triangle", "ladder"])
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--batch", type=int, default=None)
@@ -93,6 +99,10 @@ def build_workload(a):
         m, B, S = a.m or 4096, a.batch or 1, a.samples or 4096
         nets = [W.tt_caterpillar(seed=3 + b) for b in range(B)]
         return nets, m, S, f"tt_caterpillar32_bond64_phys64_fp32_m{m}_x{B}", "float32", "acyclic"
+    if a.workload == "ladder":
+        m, B, S = a.m or 4096, a.batch or 1, a.samples or 64
+        nets = [W.tt_ladder(seed=3 + b) for b in range(B)]
+        return nets, m, S, f"tt_ladder32_bond64_phys64_fp32_m{m}_x{B}", "float32", "cyclic"
     m, B, S = a.m or 256, a.batch or 64, a.samples or 256
     nets = [W.triangle(64, seed=1 + b) for b in range(B)]
     return nets, m, S, f"triangle64_fp64_normal_m{m}_x{B}", "float64", "cyclic"
@@ -105,7 +115,7 @@ def _oracle_net(workload, j):
     if workload == "batched":
         return W.random_network(4, j)
     return {"torus": lambda: W.torus(L=4, D=16, seed=2), "ttcat": lambda: W.tt_caterpillar(seed=3),
-            "triangle": lambda: W.triangle(64, seed=1)}[workload]()
+            "triangle": lambda: W.triangle(64, seed=1), "ladder": lambda: W.tt_ladder(seed=3)}[workload]()
 
 
 def _cpu_worker(args):
@@ -367,6 +377,17 @@ def main():
     # a network needs for a mean within 1e-2 of it (one standard error)
     rel_std = np.sqrt(np.maximum(st[:, 1], 0)) / norms
     need = np.maximum(1.0, np.ceil((rel_std / 1e-2) ** 2))
+    exact = None
+    if a.workload in ("ttcat", "ladder"):
+        # output-relative error against the exact FP64 contraction of each network
+        vals = np.array([T.tn_contract_exact(sp) for sp in specs])
+        rel_out = np.abs(st[:, 0] - vals) / np.abs(vals)
+        std_out = np.sqrt(np.maximum(st[:, 1], 0)) / np.abs(vals)
+        exact = {"exact": [float(v) for v in vals[:4]],
+                 "mean_estimate": [float(v) for v in st[:4, 0]],
+                 "output_relative_error_of_mean": float(np.median(rel_out)),
+                 "output_relative_std_of_one_estimate": float(np.median(std_out)),
+                 "samples_for_1e-2_output_relative": float(np.median(np.maximum(1.0, np.ceil((std_out / 1e-2) ** 2))))}
     out = {
         "metric": METRIC,
         "value": value,
@@ -391,6 +412,7 @@ def main():
                     "networks_per_s": float(len(nets) / np.sum(need) * value)},
         "kernel_ms_per_step": kt,
         "plain": plain,
+        **({"output_relative": exact} if exact is not None else {}),
     }
     plan.close()
     if not a.no_cpu_baseline:

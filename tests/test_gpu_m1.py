@@ -538,3 +538,16 @@ def test_profile_sketch_only(T, orc):
     with pytest.raises(T.TNError) as e:
         make_plan(T, nets, "float32", 256, 6, 8, flags=T.TN_FLAG_PROFILE_SKETCH)
     assert e.value.code == T.TN_ERR_ARG
+
+
+def test_tt_ladder_full_size(T, orc):
+    """The literal inner product of two tensor trains (a cyclic ladder: 64
+    cores of (64, 64, 64), 94 contractions) through the cyclic estimator at
+    m = 4096, sampled estimates against the oracle; the exact FP64
+    contraction agrees with the oracle's on a small ladder."""
+    net = W.tt_ladder()
+    plan, views = make_plan(T, [net], "float32", 4096, 2, 3)
+    check_estimates(orc, plan, views, 3, "float32")
+    small = W.tt_ladder(cores=4, bond=3, phys=2, seed=5, dtype=np.float64)
+    spec = T.NetworkSpec.from_network(small, dev(small, "float64"))
+    assert T.tn_contract_exact(spec) == pytest.approx(orc.tc_full(small), rel=1e-12, abs=1e-14)
