@@ -41,6 +41,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6   # dense FP64 matrix cores (the same figure as FP64 vector)
+FP32_MFMA_PEAK_TFLOPS = 157.3   # dense FP32 matrix cores
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense BF16 matrix cores
 
 METRIC = "sketch estimates/s at 1e-2 rel. error; % HBM roofline; batched/learned vs plain"
@@ -55,8 +56,9 @@ def parse():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--samples", type=int, default=None)
     ap.add_argument("--batch", type=int, default=None)
-    ap.add_argument("--products", default="fp64", choices=["fp64", "bf16"],
-                    help="acyclic method: SMVP products on the FP64 (default) or BF16 matrix cores")
+    ap.add_argument("--products", default="fp32", choices=["fp64", "fp32", "bf16"],
+                    help="acyclic method: SMVP products on the FP32 (default; exact operands for FP32 "
+                         "data), FP64 (the reference mode) or BF16 matrix cores")
     ap.add_argument("--dft", default="fft", choices=["fft", "bf16"],
                     help="cyclic method, m = 1024: the combine's DFTs as an LDS FFT (default) or as "
                          "32 x 32 products on the BF16 matrix cores (TN_FLAG_DFT_BF16)")
@@ -299,6 +301,9 @@ def main():
     bf16_products = a.products == "bf16" and method == "acyclic"
     if bf16_products:
         flags |= T.TN_FLAG_MFMA_BF16
+    f32_products = a.products == "fp32" and method == "acyclic" and dtype != "float64"
+    if f32_products:
+        flags |= T.TN_FLAG_MFMA_F32
     dft_bf16 = a.dft == "bf16" and method == "cyclic"
     if dft_bf16:
         flags |= T.TN_FLAG_DFT_BF16
@@ -368,8 +373,10 @@ def main():
                     "flops_per_step": flops_step}
         else:
             achieved = flops_step / (sk_ms / a.steps * 1e-3) / 1e12
-            roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None, "kernel": "m2_gemm16_kernel",
+            peak = FP32_MFMA_PEAK_TFLOPS if f32_products else FP64_MFMA_PEAK_TFLOPS
+            roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                    "frac": achieved / peak, "traffic": None,
+                    "kernel": "m2_gemm16_kernel<F32>" if f32_products else "m2_gemm16_kernel",
                     "avg_launch_ms": avg_ms, "launches": sk_n, "flops_per_step": flops_step}
     st = stats.cpu().numpy().reshape(-1, 2)
     norms = np.array([n.input_norm() for n in nets])
@@ -404,6 +411,7 @@ def main():
         "config": {"workload": name, "method": method, "networks": len(nets),
                    "samples_per_network": S, "m": m, "entries": entries,
                    **({"products": "bf16 matrix cores, fp32 accumulation"} if bf16_products else {}),
+                   **({"products": "fp32 matrix cores, fp32 accumulation"} if f32_products else {}),
                    **({"dft": "bf16 matrix cores (32 x 32 four-step), fp32 accumulation"} if dft_bf16 else {}),
                    "bytes_resident": entries * esize},
         "roofline": roof,

@@ -140,6 +140,16 @@ extern "C" {
                                    by at most about 6 2^-9 U_k to first order, and an estimate
                                    by at most 8 2^-9 (1/m) sum_j sum_k U_k prod_{k' != k}
                                    |Y_k'[j]| (the tests state the measured error) */
+#define TN_FLAG_MFMA_F32 0x800u /* TN_ACYCLIC only, FP32 or BF16 data, not with TN_FLAG_MFMA_BF16:
+                                   the SMVP products w_k = mat(X_k) G run on the FP32 matrix
+                                   cores (the operands are exact in FP32: the data, and g,
+                                   which is stored in FP32 for such data; FP32 accumulation
+                                   within a block's column range, FP64 across ranges) instead of
+                                   the FP64 ones.  The accumulation over K columns adds about
+                                   2^-24 sqrt(K) relative to each w_k per tree level; the tests
+                                   state the measured error.  The FP64 products (no flag) stay
+                                   the reference mode (TN_ERR_UNSUPPORTED with TN_CYCLIC or FP64
+                                   data) */
 #define TN_FLAG_SIZE_PILOT 0x100u   /* m <= 0: size the plan from a pilot (see tn_sketch_size) */
 #define TN_FLAG_SIZE_LEARNED 0x200u /* m <= 0: size the plan from the registered regressor */
 

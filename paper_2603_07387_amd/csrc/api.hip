@@ -130,7 +130,8 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
     return set_error(TN_ERR_ARG, "sizing flags need m <= 0");
   if (flags & ~(uint32_t)(TN_FLAG_GRAPH | TN_FLAG_PROFILE | TN_FLAG_AUTOTUNE | TN_FLAG_MFMA_BF16 |
                           TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH | TN_FLAG_PRIOR_XCORR |
-                          TN_FLAG_RESIDENT | TN_FLAG_SIZE_PILOT | TN_FLAG_SIZE_LEARNED | TN_FLAG_DFT_BF16))
+                          TN_FLAG_RESIDENT | TN_FLAG_SIZE_PILOT | TN_FLAG_SIZE_LEARNED | TN_FLAG_DFT_BF16 |
+                          TN_FLAG_MFMA_F32))
     return set_error(TN_ERR_ARG, "unknown flags 0x%x", flags);
   if ((flags & TN_FLAG_RESIDENT) && (method != TN_CYCLIC || (flags & TN_FLAG_PERSISTENT)))
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_RESIDENT applies to the cyclic method's slot kernels");
@@ -144,6 +145,10 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_PERSISTENT applies to the cyclic method");
   if ((flags & TN_FLAG_MFMA_BF16) && method != TN_ACYCLIC)
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_MFMA_BF16 applies to the acyclic method");
+  if ((flags & TN_FLAG_MFMA_F32) && (method != TN_ACYCLIC || (flags & TN_FLAG_MFMA_BF16)))
+    return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_MFMA_F32 applies to the acyclic method without BF16 products");
+  if ((flags & TN_FLAG_MFMA_F32) && nets[0].dtype == TN_F64)
+    return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_MFMA_F32 is for FP32 and BF16 data");
   if ((flags & TN_FLAG_GRAPH) && (flags & TN_FLAG_PROFILE))
     return set_error(TN_ERR_ARG, "TN_FLAG_PROFILE cannot be combined with TN_FLAG_GRAPH");
   if (m <= 0) {

@@ -674,11 +674,14 @@ struct RawW<uint16_t> {
 
 // ---------------------------------------------------------------------------
 // The product on v_mfma_f64_16x16x4f64 (A[i][k] in lane i + 16k, B[k][j] in
-// lane j + 16k, D[i][j] as element i / 4 of lane j + 16 (i % 4)); with BF
-// (TN_FLAG_MFMA_BF16) on v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i + 16 (k / 8)
-// element k % 8, B[k][j] in lane j + 16 (k / 8) element k % 8, D[i][j] in lane
-// j + 16 (i / 4) item i % 4), operands rounded to BF16, FP32 accumulation, the
-// same staging, partials and reduction in FP64.  A block of four
+// lane j + 16k, D[i][j] as element i / 4 of lane j + 16 (i % 4)); with
+// kProdBF16 (TN_FLAG_MFMA_BF16) on v_mfma_f32_16x16x32_bf16 (A[i][k] in lane
+// i + 16 (k / 8) element k % 8, B[k][j] in lane j + 16 (k / 8) element k % 8,
+// D[i][j] in lane j + 16 (i / 4) item i % 4), operands rounded to BF16, FP32
+// accumulation; with kProdF32 (TN_FLAG_MFMA_F32) on v_mfma_f32_16x16x4f32
+// (A and B as for FP64, D as for BF16), FP32 operands (exact for FP32 and BF16
+// data and for g, which is stored in FP32), FP32 accumulation.  The same
+// staging, partials and reduction in FP64 for all three.  A block of four
 // waves owns 64 rows x 64 samples and a column range; each wave a 32 x 32 corner
 // (2 x 2 accumulators of 16 x 16).  Per chunk of 16 W columns the block stages the
 // X rows and the G rows in double-buffered LDS, one 16-byte vector (W columns) per
@@ -689,6 +692,7 @@ struct RawW<uint16_t> {
 // stores: FP64 partials [split][tile][sample][64] when the columns are split,
 // else w or the estimates.
 constexpr int kG16Rows = 64, kG16Samples = 64, kG16Threads = 256, kG16Pad = 17;
+constexpr int kProdF64 = 0, kProdBF16 = 1, kProdF32 = 2;  // matrix-core product precision
 
 template <typename T, typename A>
 constexpr size_t g16_lds_bytes() {  // T: X data, A: g storage
@@ -697,8 +701,8 @@ constexpr size_t g16_lds_bytes() {  // T: X data, A: g storage
   return tiles > outb ? tiles : outb;
 }
 
-// G: storage type of g (A, or BF16 bits with BF).
-template <typename T, typename A, typename G, bool BF>
+// G: storage type of g (A, or BF16 bits with kProdBF16).
+template <typename T, typename A, typename G, int PM>
 __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     const M2Node *__restrict__ nodes, const M2Tile *__restrict__ tiles, int32_t n_tiles,
     const void *const *data, const G *__restrict__ gbuf, int64_t g_row, int64_t samples,
@@ -706,7 +710,8 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     int32_t kcols, double *__restrict__ part) {
   constexpr int W = RawW<T>::W;
   static_assert(RawW<G>::W == W, "operand widths differ");
-  static_assert(BF || sizeof(G) == sizeof(A), "BF16 g only with BF16 products");
+  static_assert(PM == kProdBF16 || sizeof(G) == sizeof(A), "BF16 g only with BF16 products");
+  constexpr bool BF = PM == kProdBF16;
   constexpr int32_t CC = 16 * W;  // columns per chunk
   constexpr int ROWV = kG16Pad;   // vectors per LDS row (16 + 1 pad)
   using V = RawW<T>;
@@ -786,7 +791,7 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     }
   };
   typedef double d4 __attribute__((ext_vector_type(4)));
-  using Acc = typename std::conditional<BF, gf32x4acc, d4>::type;
+  using Acc = typename std::conditional<PM == kProdF64, d4, gf32x4acc>::type;
   Acc acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -834,6 +839,20 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
           for (int b = 0; b < 2; ++b)
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[a], gv[b], acc[a][b], 0, 0, 0);
       }
+    } else if constexpr (PM == kProdF32) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const V a0 = xb[4 * q], a1 = xb[16 * ROWV + 4 * q];
+        const VA b0 = gbp[4 * q], b1 = gbp[16 * ROWV + 4 * q];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+          const float x0 = (float)a0.get(e), x1 = (float)a1.get(e), y0 = (float)b0.get(e), y1 = (float)b1.get(e);
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x0, y1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(x1, y1, acc[1][1], 0, 0, 0);
+        }
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -862,7 +881,7 @@ __global__ __launch_bounds__(kG16Threads) void m2_gemm16_kernel(
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        out[(ws * 32 + b * 16 + li) * (kG16Rows + 1) + wr * 32 + a * 16 + (BF ? 4 * kk + r : kk + 4 * r)] =
+        out[(ws * 32 + b * 16 + li) * (kG16Rows + 1) + wr * 32 + a * 16 + (PM == kProdF64 ? kk + 4 * r : 4 * kk + r)] =
             (double)acc[a][b][r];
   __syncthreads();
   const int orl = tid & 63;  // tile row
@@ -986,10 +1005,13 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
   auto gkp = m2_gather_kernel<T, A, G, true>;
   constexpr size_t g16 = g16_lds_bytes<T, G>();
   if (g16 > 65536) {
-    if constexpr (sizeof(G) == sizeof(A))
-      TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, false>,
+    if constexpr (sizeof(G) == sizeof(A)) {
+      TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, kProdF64>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
-    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, true>,
+      TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, kProdF32>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
+    }
+    TN_HIP_CHECK(hipFuncSetAttribute((const void *)m2_gemm16_kernel<T, A, G, kProdBF16>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)g16));
   }
   if (lds > 65536) {
@@ -1055,15 +1077,21 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
       dim3 g4((unsigned)nt, (unsigned)((n + kG16Samples - 1) / kG16Samples), (unsigned)z);
       double *part = z > 1 ? P->d_part : nullptr;
       if constexpr (sizeof(G) != sizeof(A)) {  // BF16 g: BF16 products only
-        hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, true>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt,
-                           dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+        hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, kProdBF16>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl,
+                           nt, dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
       } else {
         if (bf)
-          hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, true>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt,
-                             dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+          hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, kProdBF16>), g4, dim3(kG16Threads), g16, st, P->d_nodes,
+                             tl, nt, dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d],
+                             part);
+        else if (p->flags & TN_FLAG_MFMA_F32)
+          hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, kProdF32>), g4, dim3(kG16Threads), g16, st, P->d_nodes,
+                             tl, nt, dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d],
+                             part);
         else
-          hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, false>), g4, dim3(kG16Threads), g16, st, P->d_nodes, tl, nt,
-                             dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d], part);
+          hipLaunchKernelGGL((m2_gemm16_kernel<T, A, G, kProdF64>), g4, dim3(kG16Threads), g16, st, P->d_nodes,
+                             tl, nt, dp, gb, P->g_row, n, wb, P->w_row, est, p->S, c0, P->level_kcols[(size_t)d],
+                             part);
       }
       TN_HIP_CHECK(hipGetLastError());
       if ((rc = prof_end(p, st, TN_KERNEL_SKETCH, ev)) != TN_OK) return rc;
