@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--persistent", action="store_true",
                     help="cyclic method: the persistent fused kernel (TN_FLAG_PERSISTENT)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--error-curve", action="store_true",
+                    help="torus: the exact FP64 contraction of the first torus (tn_contract_exact) and the "
+                         "relative error of the mean of S estimates against it, S = 1 .. 4096, at "
+                         "m = 1024, 16384 and 65536")
     ap.add_argument("--no-plain", action="store_true",
                     help="skip the unbatched comparison (one plan per network)")
     ap.add_argument("--cpu-seconds", type=float, default=8.0,
@@ -275,6 +279,37 @@ def kernel_breakdown(T, specs, meth, m, S, flags, steps):
     return out
 
 
+def error_curve(T, spec, torch):
+    """The 4 x 4 bond-16 torus against its exact value: the relative error of
+    the mean of the first S estimates (fresh plans, seed 5) for S = 4^j, and
+    the spread of one estimate, at three sketch sizes.  Uniform[0,1) tensors
+    are dominated by their all-ones part, so single estimates are heavy-tailed
+    (Lemma 7's regime) and the error falls slowly and unevenly with S."""
+    import numpy as np
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    z = T.tn_contract_exact(spec)
+    t_exact = time.perf_counter() - t0
+    res = {"exact": z, "exact_seconds": t_exact,
+           "exact_main_product_flops": 4.0 * 16.0 ** 12,  # two 65536^3 products on the FP64 matrix cores
+           "m": {}}
+    S = 4096
+    for m in (1024, 16384, 65536):
+        plan = T.Plan([spec], T.TN_CYCLIC, m, S, 5)
+        smp = torch.empty(S, dtype=torch.float64, device="cuda")
+        plan.estimate(samples_out=smp)
+        y = smp.cpu().numpy()
+        plan.close()
+        sizes = [4 ** j for j in range(7)]
+        res["m"][str(m)] = {
+            "S": sizes,
+            "rel_error_of_mean": [float(abs(y[:k].mean() - z) / z) for k in sizes],
+            "rel_std_of_one_estimate": float(y.std(ddof=1) / z),
+            "rel_error_median_of_means_64_groups": float(abs(np.median(y.reshape(64, -1).mean(axis=1)) - z) / z),
+        }
+    return res
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -423,6 +458,8 @@ def main():
         **({"output_relative": exact} if exact is not None else {}),
     }
     plan.close()
+    if a.error_curve and a.workload == "torus":
+        out["error_curve"] = error_curve(T, specs[0], torch)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(a.workload, m, S, a.cpu_seconds)
     print(json.dumps(out))

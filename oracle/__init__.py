@@ -74,6 +74,8 @@ def lib():
         L.orc_tc_literal.argtypes = net + [dp]
         L.orc_tc_full.argtypes = net + [dp]
         L.orc_tc_tree.argtypes = net + [ctypes.c_int, dp]
+        L.orc_tc_torus.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), dp]
         L.orc_m1_estimate.argtypes = net + [ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint64,
                                             i64p, ctypes.c_int, dp, dp, dp]
         L.orc_m1_enumerate.argtypes = net + [ctypes.c_int64, dp, dp, i64p]
@@ -165,6 +167,18 @@ def tc_full(net):
     n = _Net(net)
     out = np.zeros(1)
     _check(lib().orc_tc_full(*n.args(), _dptr(out)), "tc_full")
+    return float(out[0])
+
+
+def tc_torus(tensors, R, C):
+    """Periodic R x C lattice contracted through its row transfer matrices;
+    tensors[r * C + c] has modes (left, right, up, down), each of size D."""
+    D = int(np.asarray(tensors[0]).shape[0])
+    arrs = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in tensors]
+    assert len(arrs) == R * C and all(a.shape == (D, D, D, D) for a in arrs)
+    ptrs = (ctypes.POINTER(ctypes.c_double) * (R * C))(*[_dptr(a) for a in arrs])
+    out = np.zeros(1)
+    _check(lib().orc_tc_torus(R, C, D, ptrs, _dptr(out)), "tc_torus")
     return float(out[0])
 
 

@@ -210,6 +210,74 @@ int orc_tc_full(int p, const int *order, const int64_t *dims, const double *cons
   return 0;
 }
 
+/*
+ * Periodic R x C lattice (Def. 1-3 for the torus): tensor (r, c) is data[r C + c]
+ * with modes (left, right, up, down), each of size D; right(r, c) meets
+ * left(r, c+1) and down(r, c) meets up(r+1, c), indices mod C and R.  Summed
+ * row by row: the row transfer matrix
+ *   T_r[(u_0..u_{C-1}), (d_0..d_{C-1})]
+ *     = sum over h_0..h_{C-1} of prod_c X_(r,c)[h_c, h_{c+1 mod C}, u_c, d_c]
+ * (the horizontal contractions of row r), and the vertical contractions join
+ * the rows' down and up indices: Z = trace(T_0 T_1 ... T_{R-1}).  Each T_r is
+ * D^C x D^C, built by summing over every (u, d, h).  Requires D^(3C) <= 2^28.
+ */
+int orc_tc_torus(int R, int C, int64_t D, const double *const *data, double *out) {
+  if (R < 1 || C < 1 || D < 1) return -1;
+  double cells = pow((double)D, 3.0 * C);
+  if (cells > 268435456.0) return -7;
+  int64_t n = 1;
+  for (int c = 0; c < C; ++c) n *= D;            /* D^C row states */
+  int64_t *u = calloc((size_t)C, sizeof(int64_t));
+  int64_t *d = calloc((size_t)C, sizeof(int64_t));
+  int64_t *h = calloc((size_t)C, sizeof(int64_t));
+  int64_t *dimsC = malloc((size_t)C * sizeof(int64_t));
+  for (int c = 0; c < C; ++c) dimsC[c] = D;
+  double *T = calloc((size_t)(n * n), sizeof(double));
+  double *P = calloc((size_t)(n * n), sizeof(double));
+  double *Q = calloc((size_t)(n * n), sizeof(double));
+  for (int r = 0; r < R; ++r) {
+    /* T_r */
+    for (int64_t i = 0; i < n * n; ++i) T[i] = 0.0;
+    for (int c = 0; c < C; ++c) u[c] = 0;
+    do {
+      for (int c = 0; c < C; ++c) d[c] = 0;
+      do {
+        double sum = 0.0;
+        for (int c = 0; c < C; ++c) h[c] = 0;
+        do {
+          double prod = 1.0;
+          for (int c = 0; c < C; ++c) {
+            const double *X = data[r * C + c];
+            int64_t lin = ((h[c] * D + h[(c + 1) % C]) * D + u[c]) * D + d[c];
+            prod *= X[lin];
+          }
+          sum += prod;
+        } while (odometer(h, dimsC, C));
+        int64_t iu = 0, id = 0;
+        for (int c = 0; c < C; ++c) { iu = iu * D + u[c]; id = id * D + d[c]; }
+        T[iu * n + id] = sum;
+      } while (odometer(d, dimsC, C));
+    } while (odometer(u, dimsC, C));
+    /* P = P T_r (P = T_0 for r = 0) */
+    if (r == 0) {
+      for (int64_t i = 0; i < n * n; ++i) P[i] = T[i];
+    } else {
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+          double acc = 0.0;
+          for (int64_t k = 0; k < n; ++k) acc += P[i * n + k] * T[k * n + j];
+          Q[i * n + j] = acc;
+        }
+      for (int64_t i = 0; i < n * n; ++i) P[i] = Q[i];
+    }
+  }
+  double tr = 0.0;
+  for (int64_t i = 0; i < n; ++i) tr += P[i * n + i];
+  *out = tr;
+  free(u); free(d); free(h); free(dimsC); free(T); free(P); free(Q);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Discrete Fourier transform, F[j][b] = exp(-2 pi i j b / m)                 */
 /* ------------------------------------------------------------------------- */

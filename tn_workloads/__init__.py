@@ -153,21 +153,23 @@ def chain(lengths, seed=0, dtype=np.float64, dist="normal"):
     return _mk(shapes, edges, rng, dist, dtype, f"chain{len(shapes)}")
 
 
-def torus(L=4, D=16, seed=2, dtype=np.float32, dist="uniform"):
-    """L x L periodic lattice of order-4 tensors (modes: left, right, up, down),
-    bond dimension D; right(r,c)-left(r,c+1) and down(r,c)-up(r+1,c) are contracted."""
+def torus(L=4, D=16, seed=2, dtype=np.float32, dist="uniform", cols=None):
+    """L x cols (default L x L) periodic lattice of order-4 tensors (modes: left,
+    right, up, down), bond dimension D, tensor (r, c) at index r cols + c;
+    right(r,c)-left(r,c+1) and down(r,c)-up(r+1,c) are contracted."""
+    C = L if cols is None else cols
     rng = np.random.default_rng(seed)
     shapes, edges = [], []
-    idx = lambda r, c: (r % L) * L + (c % L)
+    idx = lambda r, c: (r % L) * C + (c % C)
     for r in range(L):
-        for c in range(L):
+        for c in range(C):
             shapes.append((D, D, D, D))
     for r in range(L):
-        for c in range(L):
+        for c in range(C):
             k = idx(r, c)
             edges.append((4 * k + 1, 4 * idx(r, c + 1) + 0))
             edges.append((4 * k + 3, 4 * idx(r + 1, c) + 2))
-    return _mk(shapes, edges, rng, dist, dtype, f"torus{L}x{L}D{D}")
+    return _mk(shapes, edges, rng, dist, dtype, f"torus{L}x{C}D{D}")
 
 
 def tt_caterpillar(cores=32, bond=64, phys=64, seed=3, dtype=np.float32):
