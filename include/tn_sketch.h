@@ -84,10 +84,13 @@ extern "C" {
 /* Plan flags. */
 #define TN_FLAG_GRAPH 0x1u      /* capture each estimate's launches in a hipGraph and replay it */
 #define TN_FLAG_PROFILE 0x2u    /* record HIP events around every kernel launch (not with GRAPH) */
-#define TN_FLAG_AUTOTUNE 0x4u   /* first estimate times the sketching pass at each feasible
-                                   samples-per-pass value on the bound data and keeps the
-                                   fastest (that call synchronizes its stream); cached per
-                                   plan shape for the life of the process */
+#define TN_FLAG_AUTOTUNE 0x4u   /* first estimate times launch shapes on the bound data and
+                                   keeps the fastest (that call synchronizes its stream); cached
+                                   per plan shape for the life of the process.  TN_CYCLIC: the
+                                   scatter's samples per pass and accumulator banks (estimates
+                                   unchanged bit for bit); TN_ACYCLIC: the products' column-split
+                                   target and the gathers' blocks per level (the split regroups
+                                   FP64 partial sums: estimates move by rounding only) */
 #define TN_FLAG_MFMA_BF16 0x8u  /* TN_ACYCLIC only: the SMVP products w_k = mat(X_k) G run on the
                                    BF16 matrix cores (operands rounded to BF16 to nearest even,
                                    FP32 accumulation) instead of the FP64 ones; the hashes,

@@ -32,6 +32,7 @@
 //               with few tiles the columns are split over blocks and the FP64
 //               partials summed in a fixed order by m2_reduce.
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <type_traits>
@@ -101,6 +102,8 @@ struct M2Plan {
   int64_t chunk = 0;
   int32_t tcap = 4;     // slot-table entries per tensor (max over tensors, multiple of 2)
   std::vector<int32_t> node_of_tensor;  // global tensor -> node index
+  int32_t split_target = 512;   // blocks a product level aims for with its column split
+  int32_t gather_target = 0;    // blocks a gather level aims for (0: the kernel's default)
 };
 
 namespace {
@@ -1047,7 +1050,7 @@ int m2_run_t(tn_plan *p, hipStream_t st, int64_t c0, int64_t n, const int32_t *t
     // Samples per block: about 1024 blocks per level (four resident per CU;
     // six for the two-child kernel with BF16 g's 32-bit sketches).
     const int64_t nn = (int64_t)P->level_nodes[(size_t)d].size();
-    const int64_t target = pair && sizeof(G) == 2 ? 1536 : 1024;
+    const int64_t target = P->gather_target > 0 ? P->gather_target : (pair && sizeof(G) == 2 ? 1536 : 1024);
     const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, (target + nn - 1) / nn));
     dim3 g1((unsigned)nn, (unsigned)gy);
     hipLaunchKernelGGL(pair ? gkp : gk, g1, dim3(256), lds, st, P->d_nodes, P->d_level_nodes[(size_t)d],
@@ -1148,6 +1151,55 @@ int upload_vec(V **ptr, const std::vector<V> &v) {
 }
 
 }  // namespace
+
+constexpr int32_t kSplitTargetMax = 2048;
+
+// Column split of the products: a level with few 64 x 64 tiles spreads its
+// columns over up to 8 blocks per tile, towards `target` blocks (512 by
+// default: two per CU), each range still at least 8 chunks of 16 W columns.
+// Returns the partials buffer this needs, [splits][tiles][chunk][64] doubles
+// (below target x 2 x 64 x 64 entries: blocks x splits < target).  A split depth
+// d >= 1 is consumed as partials by the gathers of depth d - 1 when each parent
+// there has at most one non-leaf child, of at most 256 values (it is then loaded
+// into registers ahead of its sample).
+size_t m2_schedule(tn_plan *p, int32_t target) {
+  M2Plan *P = p->m2;
+  const int64_t chunk = P->chunk;
+  const int64_t cc = p->dtype == TN_F64 ? 32 : 64;
+  size_t part = 0;
+  P->split_target = target;
+  P->level_splits.assign(P->level_tiles.size(), 1);
+  P->level_kcols.assign(P->level_tiles.size(), 0);
+  for (size_t d = 0; d < P->level_tiles.size(); ++d) {
+    const int64_t tiles = (int64_t)P->level_tiles[d].size();
+    if (tiles == 0) continue;
+    const int64_t blocks = tiles * ((chunk + kG16Samples - 1) / kG16Samples);
+    const int64_t maxc = P->level_maxcols[d];
+    int32_t z = 1;
+    while (z < kMaxSplit && blocks * z < target && maxc >= 16 * cc * z) z *= 2;
+    const int64_t kc = ((maxc + z - 1) / z + cc - 1) / cc * cc;
+    P->level_splits[d] = z;
+    P->level_kcols[d] = (int32_t)kc;
+    if (z > 1) part = std::max(part, (size_t)z * (size_t)tiles * (size_t)chunk * kG16Rows);
+  }
+  P->level_fuse.assign(P->level_tiles.size(), 0);
+  for (size_t d = 1; d < P->level_tiles.size(); ++d) {
+    if (P->level_splits[d] <= 1 || P->level_splits[d] > kMaxSplit) continue;
+    bool ok = true;
+    for (int32_t ni : P->level_nodes[d - 1]) {
+      const M2Node &nd = P->h_nodes[(size_t)ni];
+      int nl = 0;
+      for (int i = 0; i < nd.nchild; ++i)
+        if (nd.child_tensor[i] < 0) {
+          ++nl;
+          ok = ok && nd.child_dim[i] <= 256;
+        }
+      ok = ok && nl <= 1;
+    }
+    P->level_fuse[d] = ok ? 1 : 0;
+  }
+  return part;
+}
 
 int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &chk) {
   if (p->log2m > kM2MaxLog2M)
@@ -1351,45 +1403,10 @@ int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &ch
   P->chunk = chunk;
   p->chunk = chunk;
   p->sb = 1;
-  // Column split of the FP64 products: a level with few 64 x 64 tiles spreads
-  // its columns over up to 8 blocks per tile, towards 512 blocks (two per CU),
-  // each range still at least 8 chunks of 16 W columns.  The partials buffer,
-  // [splits][tiles][chunk][64] doubles, then stays below 1024 x 64 x 64 x 8 B.
-  const int64_t cc = p->dtype == TN_F64 ? 32 : 64;
-  size_t part = 0;
-  P->level_splits.assign(P->level_tiles.size(), 1);
-  P->level_kcols.assign(P->level_tiles.size(), 0);
-  for (size_t d = 0; d < P->level_tiles.size(); ++d) {
-    const int64_t tiles = (int64_t)P->level_tiles[d].size();
-    if (tiles == 0) continue;
-    const int64_t blocks = tiles * ((chunk + kG16Samples - 1) / kG16Samples);
-    const int64_t maxc = P->level_maxcols[d];
-    int32_t z = 1;
-    while (z < kMaxSplit && blocks * z < 512 && maxc >= 16 * cc * z) z *= 2;
-    const int64_t kc = ((maxc + z - 1) / z + cc - 1) / cc * cc;
-    P->level_splits[d] = z;
-    P->level_kcols[d] = (int32_t)kc;
-    if (z > 1) part = std::max(part, (size_t)z * (size_t)tiles * (size_t)chunk * kG16Rows);
-  }
-  // A split depth d >= 1 is consumed as partials by the gathers of depth d - 1
-  // when each parent there has at most one non-leaf child, of at most 256
-  // values (it is then loaded into registers ahead of its sample).
-  P->level_fuse.assign(P->level_tiles.size(), 0);
-  for (size_t d = 1; d < P->level_tiles.size(); ++d) {
-    if (P->level_splits[d] <= 1 || P->level_splits[d] > kMaxSplit) continue;
-    bool ok = true;
-    for (int32_t ni : P->level_nodes[d - 1]) {
-      const M2Node &nd = P->h_nodes[(size_t)ni];
-      int nl = 0;
-      for (int i = 0; i < nd.nchild; ++i)
-        if (nd.child_tensor[i] < 0) {
-          ++nl;
-          ok = ok && nd.child_dim[i] <= 256;
-        }
-      ok = ok && nl <= 1;
-    }
-    P->level_fuse[d] = ok ? 1 : 0;
-  }
+  // The partials buffer holds the column split of the largest target the
+  // autotuner may choose; the default target is then applied.
+  const size_t part = m2_schedule(p, kSplitTargetMax);
+  m2_schedule(p, 512);
   int rc;
   if ((rc = upload_vec(&p->d_streams, p->h_streams)) != TN_OK) return rc;
   if ((rc = upload_vec(&P->d_nodes, P->h_nodes)) != TN_OK) return rc;
@@ -1431,6 +1448,81 @@ int m2_estimate(tn_plan *p, hipStream_t st, double *est) {
     int rc = m2_run(p, st, c0, n, est, nullptr);
     if (rc != TN_OK) return rc;
   }
+  return TN_OK;
+}
+
+// Launch shapes of the acyclic sweep (TN_FLAG_AUTOTUNE): the product levels'
+// column-split target and the gather levels' block target, each candidate
+// timed on the plan's first sample chunk (one warm-up run, then the faster of
+// two), the fastest kept.  The column split only regroups FP64 partial sums,
+// so estimates move by rounding alone.  Cached per plan shape.
+namespace {
+struct M2TuneKey {
+  int64_t nodes, g_row, w_row, m, S, chunk;
+  int dtype, device;
+  uint32_t prec;
+  bool operator==(const M2TuneKey &o) const {
+    return nodes == o.nodes && g_row == o.g_row && w_row == o.w_row && m == o.m && S == o.S && chunk == o.chunk &&
+           dtype == o.dtype && device == o.device && prec == o.prec;
+  }
+};
+std::vector<std::pair<M2TuneKey, std::pair<int32_t, int32_t>>> g_m2_tuned;
+std::mutex g_m2_tuned_mu;
+}  // namespace
+
+int m2_autotune(tn_plan *p, hipStream_t st) {
+  M2Plan *P = p->m2;
+  const M2TuneKey key{(int64_t)P->h_nodes.size(), P->g_row, P->w_row, p->m, p->S, P->chunk, p->dtype, p->device,
+                      p->flags & (TN_FLAG_MFMA_BF16 | TN_FLAG_MFMA_F32)};
+  auto apply = [&](std::pair<int32_t, int32_t> v) {
+    m2_schedule(p, v.first);
+    P->gather_target = v.second;
+  };
+  {
+    std::lock_guard<std::mutex> lk(g_m2_tuned_mu);
+    for (const auto &kv : g_m2_tuned)
+      if (kv.first == key) {
+        apply(kv.second);
+        return TN_OK;
+      }
+  }
+  const int64_t n = std::min(P->chunk, p->S);
+  const uint32_t saved_flags = p->flags;
+  p->flags &= ~(uint32_t)(TN_FLAG_PROFILE | TN_FLAG_PROFILE_SKETCH);  // no events inside the timing runs
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = TN_OK;
+  if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+      hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess)
+    rc = set_error(TN_ERR_HIP, "autotune: event create");
+  std::pair<int32_t, int32_t> best{512, 0};
+  float best_ms = 1e30f;
+  for (int32_t split : {128, 256, 512, 1024, kSplitTargetMax}) {
+    for (int32_t gather : {0, 512, 2048, 4096}) {
+      if (rc != TN_OK) break;
+      apply({split, gather});
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 3 && rc == TN_OK; ++rep) {
+        float ms = 0.f;
+        if (hipEventRecord(e0, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
+        if (rc == TN_OK) rc = m2_run(p, st, 0, n, p->d_est, nullptr);
+        if (rc == TN_OK && hipEventRecord(e1, st) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: event record");
+        if (rc == TN_OK && hipEventSynchronize(e1) != hipSuccess) rc = set_error(TN_ERR_HIP, "autotune: sync");
+        if (rc == TN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) ms_min = std::min(ms_min, ms);
+      }
+      if (rc == TN_OK && ms_min < best_ms) {
+        best_ms = ms_min;
+        best = {split, gather};
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  p->flags = saved_flags;
+  apply(best);
+  if (rc != TN_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_m2_tuned_mu);
+  g_m2_tuned.push_back({key, best});
   return TN_OK;
 }
 

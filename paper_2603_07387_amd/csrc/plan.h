@@ -186,6 +186,7 @@ int plan_kernel_time(tn_plan *p, int kind, double *ms, int64_t *launches);
 // acyclic method (m2.hip)
 int m2_build(tn_plan *p, const tn_network *nets, const std::vector<NetCheck> &chk);
 int m2_estimate(tn_plan *p, hipStream_t st, double *est);
+int m2_autotune(tn_plan *p, hipStream_t st);
 int m2_get_sketches(tn_plan *p, int64_t first, int64_t count, hipStream_t st, double *out);
 void m2_release(tn_plan *p);
 

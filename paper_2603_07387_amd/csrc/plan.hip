@@ -737,8 +737,8 @@ int plan_estimate(tn_plan *p, const tn_network *nets, hipStream_t st, double *st
                   double *samples_out) {
   int rc = plan_bind(p, nets, st);
   if (rc != TN_OK) return rc;
-  if ((p->flags & TN_FLAG_AUTOTUNE) && !p->tuned && p->method == TN_CYCLIC) {
-    if ((rc = m1_autotune(p, st)) != TN_OK) return rc;
+  if ((p->flags & TN_FLAG_AUTOTUNE) && !p->tuned) {
+    if ((rc = p->method == TN_CYCLIC ? m1_autotune(p, st) : m2_autotune(p, st)) != TN_OK) return rc;
     p->tuned = true;
   }
   double *est = samples_out ? samples_out : p->d_est;

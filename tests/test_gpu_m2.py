@@ -240,3 +240,34 @@ def test_bitwise_deterministic(T, orc):
     _, a = run(plan)
     _, b = run(plan)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotuned_caterpillar(T, orc, prec):
+    """TN_FLAG_AUTOTUNE on the acyclic sweep (column-split and gather block
+    targets timed on the first chunk): at the benchmark's shape the tuned
+    plan's estimates match the oracle (FP32 bar; FP32 products: the bar of
+    test_gpu_m2_f32), differ from the default schedule's within that bar (the
+    regrouping of partial sums), and repeat bit for bit."""
+    import torch
+    net = W.tt_caterpillar()
+    extra = T.TN_FLAG_MFMA_F32 if prec == "fp32" else 0
+    tuned, views = make_plan(T, [net], "float32", 4096, 4096, 0, flags=T.TN_FLAG_AUTOTUNE | extra)
+    base, _ = make_plan(T, [net], "float32", 4096, 4096, 0, flags=extra)
+    _, a = run(tuned)
+    _, a2 = run(tuned)
+    _, b = run(base)
+    assert np.array_equal(a, a2)
+    from test_gpu_m2_f32 import bar as bar32, widest
+    from test_gpu_m2_bf16 import subtree_levels
+    L = max(subtree_levels(net).values())
+    tol = TAU["float32"] if prec == "fp64" else bar32(L, widest(net))
+    # w and g are stored in FP32 between levels, so a regrouped FP64 sum that
+    # rounds to a neighbouring FP32 value carries into the levels above
+    regroup = tol
+    for r in (0, 3, 2047, 4095):
+        o = orc.m2_estimate(views[0], 4096, 0, r, root=0, want_trace=True)
+        scale = np.linalg.norm(o["x"][0]) * np.linalg.norm(o["r_root"])
+        assert abs(a[0, r] - o["estimate"]) <= tol * scale, r
+        assert abs(a[0, r] - b[0, r]) <= regroup * scale, r
+    torch.cuda.synchronize()
