@@ -33,7 +33,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tn_oracle.c")
-_LIB = os.path.join(_HERE, "libtn_oracle.so")
+# TN_ORACLE_SANITIZE=1: build and load an AddressSanitizer + UndefinedBehavior-
+# Sanitizer copy instead (the process must preload gcc's libasan).
+_SAN = os.environ.get("TN_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libtn_oracle_san.so" if _SAN else "libtn_oracle.so")
 _lib = None
 
 STREAM_TSKETCH = 1 << 62
@@ -44,7 +47,9 @@ def build(force=False):
     """Compile tn_oracle.c with gcc (plain -O2, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared",
+        san = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined"] if _SAN else []
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", *san,
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

@@ -41,7 +41,9 @@ TN_KERNEL_HASH, TN_KERNEL_SKETCH, TN_KERNEL_COMBINE, TN_KERNEL_STATS = 0, 1, 2, 
 _DTYPES = {torch.float64: TN_F64, torch.float32: TN_F32, torch.bfloat16: TN_BF16}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "libtnsketch.so")
+# TN_SKETCH_LIB names another build of the same library (the host-side
+# sanitizer build of build_sanitize.py); by default the in-tree build.
+_LIBPATH = os.environ.get("TN_SKETCH_LIB") or os.path.join(_HERE, "libtnsketch.so")
 _lib = None
 
 
