@@ -438,6 +438,56 @@ def evaluate(sel, pairs, pilot_m=1024, pilot_S=16, eps=1e-2, z=2.0, seed=99, ver
     return rows
 
 
+def work_curves(sel, pairs, zs=(1.0, 1.5, 2.0, 3.0, 4.0, 6.0), pilot_m=1024, pilot_S=16, eps=1e-2, seed=77):
+    """Hit rate against total work for both selectors as the confidence factor z
+    varies (delta = 1/z^2): per network one pilot run, then for every z the
+    learned and the pilot's (m, S), each run with fresh seeds and judged against
+    the exact contraction.  Returns {"learned": [(z, work, hits)], "pilot": [...],
+    "networks": n}; the pilot's work includes its pilot samples."""
+    out = {"learned": {z: [0.0, 0] for z in zs}, "pilot": {z: [0.0, 0] for z in zs}}
+    n = 0
+    for i, (net, method) in enumerate(pairs):
+        specs = _specs([net])
+        try:
+            exact = B.tn_contract_exact(specs[0])
+        except B.TNError:
+            continue
+        n += 1
+        st = stats_of(specs)[0]
+        norm = float(np.sqrt(np.prod(st[:, 1])))
+        stc = _structure(net)
+        m0 = pilot_m if pilot_m in LADDER[method] else LADDER[method][-1]
+        pilot = run_estimates(specs, method, m0, pilot_S, seed + 7919 * i)
+        v0 = max(pilot[0, 1] / (norm * norm), 1e-300)
+        lp = {m: math.log(v0 * m0 / m) for m in LADDER[method]}
+        w_pilot = pilot_S * work_per_sample(net, method, m0, stc)
+        ll = sel.logv(net, st, method, stc)
+        for j, z in enumerate(zs):
+            for kind, logv, extra in (("learned", ll, 0.0), ("pilot", lp, w_pilot)):
+                m, S, w = choose(net, method, logv, eps, z, st=stc)
+                est = run_estimates(specs, method, m, S, seed + 104729 * i + 15485863 * j + (kind == "pilot"))[0, 0]
+                out[kind][z][0] += w + extra
+                out[kind][z][1] += int(abs(est - exact) / norm <= eps)
+        del specs
+    res = {"networks": n}
+    for kind in ("learned", "pilot"):
+        res[kind] = [(z, out[kind][z][0], out[kind][z][1] / max(n, 1)) for z in zs]
+    return res
+
+
+def hit_at_work(curve, work):
+    """A curve's hit rate at the given total work, linear in log(work) between
+    its points (clamped at the ends)."""
+    pts = sorted((math.log(w), h) for _, w, h in curve)
+    x = math.log(work)
+    if x <= pts[0][0]:
+        return pts[0][1]
+    for (x0, h0), (x1, h1) in zip(pts, pts[1:]):
+        if x <= x1:
+            return h0 + (h1 - h0) * (x - x0) / max(x1 - x0, 1e-300)
+    return pts[-1][1]
+
+
 def summarize(rows, eps=1e-2):
     if not rows:
         return {"networks": 0}

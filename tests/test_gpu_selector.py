@@ -133,3 +133,29 @@ def test_bound_driven_sizing_against_learned(trained):
     assert hit_l >= 0.8
     assert work_b > work_l
     T.tn_set_size_selector(None, 0.0, 1.0, 0.0)
+
+
+def test_equal_work_curves(trained):
+    """Hit rate against total work as the confidence factor z varies (delta =
+    1/z^2), both selectors, held-out networks judged against the exact
+    contraction.  On the batched random workload the learned choice hits more
+    often than the pilot's at the pilot's own work for z = 1, 1.5, 2 (the
+    learned curve read off by interpolation in log work).  On the held-out
+    families (rings, tori, caterpillars, random cyclic) the learned choices
+    cost far more work than the pilot's at every z; the curves are printed,
+    and both selectors must reach 0.8 somewhere on their curves."""
+    from paper_2603_07387_amd import selector as S
+    sel = trained[0]
+    batch = S.work_curves(sel, S.batch_networks(60, start=1000))
+    fams = S.work_curves(sel, S.family_networks(60, 43, held_out=True))
+    for name, c in (("batch", batch), ("families", fams)):
+        print(name, c["networks"], "networks")
+        for kind in ("learned", "pilot"):
+            print(" ", kind, [(z, f"{w:.3g}", round(h, 3)) for z, w, h in c[kind]])
+    assert batch["networks"] >= 40 and fams["networks"] >= 40
+    for z, w, h in batch["pilot"]:
+        if z <= 2.0:
+            assert S.hit_at_work(batch["learned"], w) >= h, (z, w, h)
+    for c in (batch, fams):
+        assert max(h for _, _, h in c["learned"]) >= 0.8
+        assert max(h for _, _, h in c["pilot"]) >= 0.8
