@@ -1,7 +1,8 @@
 """Throughput benchmark of the sketching estimators on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload torus|batched|ttcat|triangle]
-                    [--m M] [--samples S] [--batch B] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload batched|torus|ttcat|triangle|ladder]
+                    [--m M] [--samples S] [--batch B] [--products fp32|fp64|bf16] [--dft fft|bf16]
+                    [--persistent] [--error-curve] [--no-cpu-baseline] [--no-plain]
 
 A step is one full pass of the estimator over one batch of synthetic input
 already resident in HBM: hash generation, the sketching pass over every tensor,
@@ -11,13 +12,15 @@ network in the batch.  Prints one JSON line.
 Workloads (all inputs seeded and synthetic):
   batched   4096 random connected cyclic networks, 3-12 tensors, bonds
             U{2..32}, FP32 N(0,1), cyclic estimator, m = 1024, S = 16
-            (1.16 GB resident).  Default.
+            (1.16 GB resident); the combine's DFTs on the BF16 matrix cores
+            unless --dft fft.  Default.
   torus     4 x 4 periodic lattice of order-4 tensors, bond 16, FP32 U[0,1),
             cyclic estimator, m = 1024; a batch of B independent tori
             (B = 256: 1 GiB resident).
   ttcat     tensor-train caterpillar (32 cores (1,64,64)..(64,64,1) with their
             physical legs contracted against vectors), FP32 N(0,1/64), acyclic
-            estimator, m = 4096, S = 4096 samples.
+            estimator, m = 4096, S = 4096 samples; products on the FP32 matrix
+            cores unless --products says otherwise.
   triangle  three 64 x 64 FP64 N(0,1) matrices, tr(ABC), m = 256.
   ladder    the literal inner product of two such tensor trains (a cyclic
             ladder of 64 cores, 94 contractions), cyclic estimator,
@@ -59,9 +62,10 @@ def parse():
     ap.add_argument("--products", default="fp32", choices=["fp64", "fp32", "bf16"],
                     help="acyclic method: SMVP products on the FP32 (default; exact operands for FP32 "
                          "data), FP64 (the reference mode) or BF16 matrix cores")
-    ap.add_argument("--dft", default="fft", choices=["fft", "bf16"],
-                    help="cyclic method, m = 1024: the combine's DFTs as an LDS FFT (default) or as "
-                         "32 x 32 products on the BF16 matrix cores (TN_FLAG_DFT_BF16)")
+    ap.add_argument("--dft", default=None, choices=["fft", "bf16"],
+                    help="cyclic method, m = 1024: the combine's DFTs as an LDS FFT or as 32 x 32 products "
+                         "on the BF16 matrix cores (TN_FLAG_DFT_BF16); default bf16 for the batched workload "
+                         "(its configuration names BF16 matrix-core contractions), fft otherwise")
     ap.add_argument("--persistent", action="store_true",
                     help="cyclic method: the persistent fused kernel (TN_FLAG_PERSISTENT)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -339,7 +343,8 @@ def main():
     f32_products = a.products == "fp32" and method == "acyclic" and dtype != "float64"
     if f32_products:
         flags |= T.TN_FLAG_MFMA_F32
-    dft_bf16 = a.dft == "bf16" and method == "cyclic"
+    dft = a.dft or ("bf16" if a.workload == "batched" and m == 1024 and dtype != "float64" else "fft")
+    dft_bf16 = dft == "bf16" and method == "cyclic"
     if dft_bf16:
         flags |= T.TN_FLAG_DFT_BF16
     persistent = a.persistent and method == "cyclic"
