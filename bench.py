@@ -1,7 +1,7 @@
 """Throughput benchmark of the sketching estimators on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--workload batched|torus|ttcat|triangle|ladder]
-                    [--m M] [--samples S] [--batch B] [--products fp32|fp64|bf16] [--dft fft|bf16]
+                    [--m M] [--samples S] [--batch B] [--products fp32|fp64|bf16] [--dft fft|bf16|fp8]
                     [--persistent] [--error-curve] [--no-cpu-baseline] [--no-plain]
 
 A step is one full pass of the estimator over one batch of synthetic input
@@ -62,10 +62,11 @@ def parse():
     ap.add_argument("--products", default="fp32", choices=["fp64", "fp32", "bf16"],
                     help="acyclic method: SMVP products on the FP32 (default; exact operands for FP32 "
                          "data), FP64 (the reference mode) or BF16 matrix cores")
-    ap.add_argument("--dft", default=None, choices=["fft", "bf16"],
+    ap.add_argument("--dft", default=None, choices=["fft", "bf16", "fp8"],
                     help="cyclic method, m = 1024: the combine's DFTs as an LDS FFT or as 32 x 32 products "
-                         "on the BF16 matrix cores (TN_FLAG_DFT_BF16); default bf16 for the batched workload "
-                         "(its configuration names BF16 matrix-core contractions), fft otherwise")
+                         "on the BF16 (TN_FLAG_DFT_BF16) or FP8 (TN_FLAG_DFT_FP8) matrix cores; default bf16 "
+                         "for the batched workload (its configuration names BF16 matrix-core contractions), "
+                         "fft otherwise")
     ap.add_argument("--persistent", action="store_true",
                     help="cyclic method: the persistent fused kernel (TN_FLAG_PERSISTENT)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -347,6 +348,9 @@ def main():
     dft_bf16 = dft == "bf16" and method == "cyclic"
     if dft_bf16:
         flags |= T.TN_FLAG_DFT_BF16
+    dft_fp8 = dft == "fp8" and method == "cyclic"
+    if dft_fp8:
+        flags |= T.TN_FLAG_DFT_FP8
     persistent = a.persistent and method == "cyclic"
     if persistent:
         flags |= T.TN_FLAG_PERSISTENT
@@ -453,6 +457,7 @@ def main():
                    **({"products": "bf16 matrix cores, fp32 accumulation"} if bf16_products else {}),
                    **({"products": "fp32 matrix cores, fp32 accumulation"} if f32_products else {}),
                    **({"dft": "bf16 matrix cores (32 x 32 four-step), fp32 accumulation"} if dft_bf16 else {}),
+                   **({"dft": "fp8 (e4m3) matrix cores (32 x 32 four-step), fp32 accumulation"} if dft_fp8 else {}),
                    "bytes_resident": entries * esize},
         "roofline": roof,
         "at_1e-2": {"median_input_relative_std": float(np.median(rel_std)),

@@ -143,6 +143,17 @@ extern "C" {
                                    by at most about 6 2^-9 U_k to first order, and an estimate
                                    by at most 8 2^-9 (1/m) sum_j sum_k U_k prod_{k' != k}
                                    |Y_k'[j]| (the tests state the measured error) */
+#define TN_FLAG_DFT_FP8 0x1000u /* as TN_FLAG_DFT_BF16 (and not with it), on the FP8 matrix cores:
+                                   OCP E4M3 operands (3 mantissa bits), FP32 accumulation.
+                                   The sketch and the twiddled intermediate are each scaled
+                                   by a power of two so that their block maximum lies in
+                                   [128, 256), then rounded stochastically (random bits from
+                                   a hash of network, sample, tensor and element: unbiased,
+                                   below one ulp, 2^-3 relative); the DFT constants are two
+                                   E4M3 terms each (about 2^-8); the scales are undone
+                                   exactly in FP64.  The estimator stays unbiased; its
+                                   rounding noise, a fraction of the estimator's own
+                                   spread, is stated by the tests */
 #define TN_FLAG_MFMA_F32 0x800u /* TN_ACYCLIC only, FP32 or BF16 data, not with TN_FLAG_MFMA_BF16:
                                    the SMVP products w_k = mat(X_k) G run on the FP32 matrix
                                    cores (the operands are exact in FP32: the data, and g,

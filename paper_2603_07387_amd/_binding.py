@@ -35,6 +35,7 @@ TN_FLAG_SIZE_PILOT = 0x100
 TN_FLAG_SIZE_LEARNED = 0x200
 TN_FLAG_DFT_BF16 = 0x400
 TN_FLAG_MFMA_F32 = 0x800
+TN_FLAG_DFT_FP8 = 0x1000
 TN_SIZE_BOUND, TN_SIZE_PILOT, TN_SIZE_LEARNED = 0, 1, 2
 TN_KERNEL_HASH, TN_KERNEL_SKETCH, TN_KERNEL_COMBINE, TN_KERNEL_STATS = 0, 1, 2, 3
 

@@ -131,12 +131,15 @@ int tn_sketch_plan(const tn_network *nets, int32_t n_nets, int32_t method, int64
   if (flags & ~(uint32_t)(TN_FLAG_GRAPH | TN_FLAG_PROFILE | TN_FLAG_AUTOTUNE | TN_FLAG_MFMA_BF16 |
                           TN_FLAG_PERSISTENT | TN_FLAG_PROFILE_SKETCH | TN_FLAG_PRIOR_XCORR |
                           TN_FLAG_RESIDENT | TN_FLAG_SIZE_PILOT | TN_FLAG_SIZE_LEARNED | TN_FLAG_DFT_BF16 |
-                          TN_FLAG_MFMA_F32))
+                          TN_FLAG_MFMA_F32 | TN_FLAG_DFT_FP8))
     return set_error(TN_ERR_ARG, "unknown flags 0x%x", flags);
   if ((flags & TN_FLAG_RESIDENT) && (method != TN_CYCLIC || (flags & TN_FLAG_PERSISTENT)))
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_RESIDENT applies to the cyclic method's slot kernels");
   if ((flags & TN_FLAG_DFT_BF16) && (method != TN_CYCLIC || (flags & TN_FLAG_PERSISTENT)))
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_DFT_BF16 applies to the cyclic method's two-kernel path");
+  if ((flags & TN_FLAG_DFT_FP8) && (method != TN_CYCLIC || (flags & (TN_FLAG_PERSISTENT | TN_FLAG_DFT_BF16))))
+    return set_error(TN_ERR_UNSUPPORTED,
+                     "TN_FLAG_DFT_FP8 applies to the cyclic method's two-kernel path, without TN_FLAG_DFT_BF16");
   if ((flags & TN_FLAG_PRIOR_XCORR) && method != TN_CYCLIC)
     return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_PRIOR_XCORR applies to the cyclic method");
   if ((flags & TN_FLAG_PROFILE_SKETCH) && !(flags & TN_FLAG_PROFILE))

@@ -333,11 +333,18 @@ int permute(Mem &mem, DTensor *T, const std::vector<int> &to) {
     out.dims.push_back(T->dims[j]);
   }
   int rc = mem.alloc(&out);
-  if (rc != TN_OK) return rc;
+  if (rc != TN_OK) {
+    mem.release(&out);
+    return rc;
+  }
   if (!mem.dry) {
     hipLaunchKernelGGL(permute_f64_kernel, dim3(grid_for(out.size)), dim3(256), 0, mem.st, d, T->ptr, out.size,
                        out.ptr);
-    TN_HIP_CHECK(hipGetLastError());
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      mem.release(&out);
+      return set_error(TN_ERR_HIP, "exact contraction: %s", hipGetErrorString(e));
+    }
   }
   mem.release(T);
   *T = out;
@@ -362,7 +369,8 @@ int sum_block(const DTensor &T, const std::vector<int> &sum, std::vector<int> *o
   return tail ? 1 : head ? -1 : 0;
 }
 
-// C = contraction of A and B over their shared labels; A and B are consumed.
+// C = contraction of A and B over their shared labels.  A and B are consumed
+// on every path; on an error C holds nothing.
 int contract_pair(Mem &mem, DTensor *A, DTensor *B, DTensor *C) {
   std::vector<int> sum, keep_a, keep_b;
   std::vector<int64_t> kd_a, kd_b;
@@ -383,8 +391,25 @@ int contract_pair(Mem &mem, DTensor *A, DTensor *B, DTensor *C) {
       kd_b.push_back(B->dims[i]);
       N *= B->dims[i];
     }
+  double *part = nullptr;
+  int64_t splits = 1, kchunk = K;
+  bool c_held = false;  // C counted by mem (allocated, or its allocation attempted)
+  // every exit releases what the step holds
+  auto finish = [&](int rc) {
+    if (part || (mem.dry && splits > 1)) mem.drop_scratch(part, splits * M * N);
+    part = nullptr;
+    splits = 1;
+    if (rc != TN_OK && c_held) mem.release(C);
+    mem.release(A);
+    mem.release(B);
+    return rc;
+  };
+  auto launched = [&]() {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TN_OK : set_error(TN_ERR_HIP, "exact contraction: %s", hipGetErrorString(e));
+  };
   if (keep_a.size() + keep_b.size() > (size_t)kMaxLabels)
-    return set_error(TN_ERR_UNSUPPORTED, "exact contraction: more than %d labels", kMaxLabels);
+    return finish(set_error(TN_ERR_UNSUPPORTED, "exact contraction: more than %d labels", kMaxLabels));
   const bool thin = M < kSkinny || N < kSkinny;
   std::vector<int> oa, ob;
   int pa = sum_block(*A, sum, &oa), pb = sum_block(*B, sum, &ob);
@@ -403,21 +428,21 @@ int contract_pair(Mem &mem, DTensor *A, DTensor *B, DTensor *C) {
   if (a_ok && b_ok && oa != ob) {
     // same blocks, different internal order: permute the smaller operand
     if (A->size <= B->size) {
-      if ((rc = permute(mem, A, pa == 1 ? concat(keep_a, ob) : concat(ob, keep_a))) != TN_OK) return rc;
+      if ((rc = permute(mem, A, pa == 1 ? concat(keep_a, ob) : concat(ob, keep_a))) != TN_OK) return finish(rc);
       oa = ob;
     } else {
-      if ((rc = permute(mem, B, pb == 1 ? concat(keep_b, oa) : concat(oa, keep_b))) != TN_OK) return rc;
+      if ((rc = permute(mem, B, pb == 1 ? concat(keep_b, oa) : concat(oa, keep_b))) != TN_OK) return finish(rc);
       ob = oa;
     }
   } else {
     if (!a_ok) {
       const std::vector<int> &o = b_ok ? ob : oa;
-      if ((rc = permute(mem, A, concat(keep_a, o))) != TN_OK) return rc;
+      if ((rc = permute(mem, A, concat(keep_a, o))) != TN_OK) return finish(rc);
       pa = 1;
       oa = o;
     }
     if (!b_ok) {
-      if ((rc = permute(mem, B, thin ? concat(keep_b, oa) : concat(oa, keep_b))) != TN_OK) return rc;
+      if ((rc = permute(mem, B, thin ? concat(keep_b, oa) : concat(oa, keep_b))) != TN_OK) return finish(rc);
       pb = thin ? 1 : -1;
       ob = oa;
     }
@@ -426,53 +451,55 @@ int contract_pair(Mem &mem, DTensor *A, DTensor *B, DTensor *C) {
   C->dims = kd_a;
   C->dims.insert(C->dims.end(), kd_b.begin(), kd_b.end());
   C->size = M * N;
-  if ((rc = mem.alloc(C)) != TN_OK) return rc;
   const bool at = pa == -1 && M > 1, bt = pb == 1 && N > 1;  // A as K x M; B as N x K
-  double *part = nullptr;
-  int64_t splits = 1, kchunk = K;
+  const int64_t tiles_m = (M + kGT - 1) / kGT, tiles_n = (N + kGT - 1) / kGT, tiles = tiles_m * tiles_n;
   if (thin) {
     const int64_t waves = M * N;
     splits = std::max<int64_t>(1, std::min<int64_t>((K + 4095) / 4096, (8192 + waves - 1) / waves));
     kchunk = (K + splits - 1) / splits;
     splits = std::max<int64_t>(1, (K + kchunk - 1) / kchunk);
-    if (splits > 65535 || (M * N + 3) / 4 > 0x7fffffffLL)
-      return set_error(TN_ERR_UNSUPPORTED, "exact contraction: thin product %lld x %lld x %lld", (long long)M,
-                       (long long)N, (long long)K);
-    if (splits > 1 && (rc = mem.scratch(&part, splits * M * N)) != TN_OK) return rc;
-    if (!mem.dry) {
-      hipLaunchKernelGGL(gemm_thin_kernel, dim3((unsigned)((M * N + 3) / 4), (unsigned)splits), dim3(256), 0, mem.st,
-                         A->ptr, B->ptr, M, N, K, kchunk, part ? part : C->ptr);
-      TN_HIP_CHECK(hipGetLastError());
+    if (splits > 65535 || (M * N + 3) / 4 > 0x7fffffffLL) {
+      splits = 1;
+      return finish(set_error(TN_ERR_UNSUPPORTED, "exact contraction: thin product %lld x %lld x %lld",
+                              (long long)M, (long long)N, (long long)K));
     }
   } else {
-    const int64_t tiles_m = (M + kGT - 1) / kGT, tiles_n = (N + kGT - 1) / kGT, tiles = tiles_m * tiles_n;
-    if (tiles > 0x7fffffffLL) return set_error(TN_ERR_UNSUPPORTED, "exact contraction: %lld tiles", (long long)tiles);
+    if (tiles > 0x7fffffffLL)
+      return finish(set_error(TN_ERR_UNSUPPORTED, "exact contraction: %lld tiles", (long long)tiles));
     if (tiles < 1024 && K >= 1024) {
       splits = std::min<int64_t>((1024 + tiles - 1) / tiles, K / 512);
       kchunk = ((K + splits - 1) / splits + kGK - 1) / kGK * kGK;
       splits = (K + kchunk - 1) / kchunk;
     }
-    if (splits > 1 && (rc = mem.scratch(&part, splits * M * N)) != TN_OK) return rc;
-    if (!mem.dry) {
+  }
+  c_held = true;
+  if ((rc = mem.alloc(C)) != TN_OK) {
+    splits = 1;
+    return finish(rc);
+  }
+  if (splits > 1 && (rc = mem.scratch(&part, splits * M * N)) != TN_OK) {
+    splits = 1;
+    return finish(rc);
+  }
+  if (!mem.dry) {
+    if (thin) {
+      hipLaunchKernelGGL(gemm_thin_kernel, dim3((unsigned)((M * N + 3) / 4), (unsigned)splits), dim3(256), 0, mem.st,
+                         A->ptr, B->ptr, M, N, K, kchunk, part ? part : C->ptr);
+    } else {
       const dim3 g((unsigned)tiles, (unsigned)splits);
       auto k = at ? (bt ? gemm_f64_kernel<true, true> : gemm_f64_kernel<true, false>)
                   : (bt ? gemm_f64_kernel<false, true> : gemm_f64_kernel<false, false>);
       hipLaunchKernelGGL(k, g, dim3(256), 0, mem.st, A->ptr, B->ptr, C->ptr, M, N, K, tiles_m, tiles_n, kchunk,
                          part);
-      TN_HIP_CHECK(hipGetLastError());
     }
-  }
-  if (part || (mem.dry && splits > 1)) {
-    if (!mem.dry) {
+    if ((rc = launched()) != TN_OK) return finish(rc);
+    if (part) {
       hipLaunchKernelGGL(gemm_reduce_kernel, dim3(grid_for(M * N)), dim3(256), 0, mem.st, part, M * N, splits,
                          C->ptr);
-      TN_HIP_CHECK(hipGetLastError());
+      if ((rc = launched()) != TN_OK) return finish(rc);
     }
-    mem.drop_scratch(part, splits * M * N);
   }
-  mem.release(A);
-  mem.release(B);
-  return TN_OK;
+  return finish(TN_OK);
 }
 
 // Contraction tree over the tensors of one component: node i < n is tensor i,
@@ -736,7 +763,10 @@ int contract_exact(const tn_network *net, hipStream_t st, double *out) {
     else
       hipLaunchKernelGGL(bf16_to_f64_kernel, dim3(g), dim3(256), 0, st, (const uint16_t *)net->data[k], T.size,
                          T.ptr);
-    TN_HIP_CHECK(hipGetLastError());
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) {
+      cleanup();
+      return set_error(TN_ERR_HIP, "exact contraction: %s", hipGetErrorString(e));
+    }
     // Traces inside the tensor.
     std::vector<int> sum;
     std::vector<int64_t> sd;
@@ -777,14 +807,17 @@ int contract_exact(const tn_network *net, hipStream_t st, double *out) {
     }
     DTensor C = sh;
     C.ptr = nullptr;
-    if ((rc = mem.alloc(&C)) != TN_OK) {
+    if ((rc = mem.alloc(&C)) != TN_OK) {  // (C.ptr stays null on failure)
       cleanup();
       return rc;
     }
     hipLaunchKernelGGL(trace_kernel, dim3(grid_for(C.size)), dim3(256), 0, st, d, T.ptr, C.size, C.ptr);
-    TN_HIP_CHECK(hipGetLastError());
     mem.release(&T);
-    T = C;
+    T = C;  // owned by ts from here, so cleanup() frees it on any later error
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) {
+      cleanup();
+      return set_error(TN_ERR_HIP, "exact contraction: %s", hipGetErrorString(e));
+    }
   }
   double result = 1.0;
   for (int c = 0; c < n_comp && rc == TN_OK; ++c) {

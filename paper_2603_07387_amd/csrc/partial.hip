@@ -311,7 +311,7 @@ extern "C" int tn_partial_plan(const tn_network *net, int64_t m, int64_t samples
   if (samples < 1) return set_error(TN_ERR_ARG, "samples = %lld", (long long)samples);
   if (m < 1 || (m & (m - 1)) != 0) return set_error(TN_ERR_ARG, "m = %lld is not a power of two", (long long)m);
   if (flags & ~(uint32_t)(TN_FLAG_GRAPH | TN_FLAG_PROFILE | TN_FLAG_AUTOTUNE | TN_FLAG_PROFILE_SKETCH |
-                          TN_FLAG_PRIOR_XCORR | TN_FLAG_DFT_BF16))
+                          TN_FLAG_PRIOR_XCORR | TN_FLAG_DFT_BF16 | TN_FLAG_DFT_FP8))
     return set_error(TN_ERR_ARG, "flags 0x%x not offered for partial plans", flags);
   if ((flags & TN_FLAG_PROFILE_SKETCH) && !(flags & TN_FLAG_PROFILE))
     return set_error(TN_ERR_ARG, "TN_FLAG_PROFILE_SKETCH needs TN_FLAG_PROFILE");

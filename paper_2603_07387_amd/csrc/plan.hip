@@ -130,8 +130,8 @@ int m1_check_m(tn_plan *p) {
   if (p->log2m > kMaxLog2M1)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: m = %lld exceeds %d", (long long)p->m,
                      1 << kMaxLog2M1);
-  if ((p->flags & TN_FLAG_DFT_BF16) && (p->m != 1024 || p->dtype == TN_F64))
-    return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_DFT_BF16: m = 1024 with FP32 or BF16 data only");
+  if ((p->flags & (TN_FLAG_DFT_BF16 | TN_FLAG_DFT_FP8)) && (p->m != 1024 || p->dtype == TN_F64))
+    return set_error(TN_ERR_UNSUPPORTED, "TN_FLAG_DFT_BF16 / TN_FLAG_DFT_FP8: m = 1024 with FP32 or BF16 data only");
   p->two_pass = (size_t)p->m * 2 * as > p->max_lds;
   if (p->two_pass && p->log2m < kMaxLog2Acc)
     return set_error(TN_ERR_UNSUPPORTED, "cyclic method: the m-point FFT needs %zu bytes of LDS",
@@ -419,10 +419,11 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
                                  (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, p->d_cbuf,
                                  p->d_partial, est, st);
     else
-      rc = (p->flags & TN_FLAG_DFT_BF16)
+      rc = (p->flags & (TN_FLAG_DFT_BF16 | TN_FLAG_DFT_FP8))
                ? launch_m1_combine_dft32(p->d_nets, p->n_nets, p->d_cbeg ? p->d_cbeg : p->d_tslot,
                                          p->d_cbeg ? p->d_cend : p->d_tslot + 1, p->d_ybuf,
-                                         (int64_t)p->h_slots.size(), n, c0, p->S, est, st)
+                                         (int64_t)p->h_slots.size(), n, c0, p->S, est,
+                                         (p->flags & TN_FLAG_DFT_FP8) != 0, st)
                : launch_m1_combine(p->d_nets, p->n_nets, p->d_cbeg ? p->d_cbeg : p->d_tslot,
                                    p->d_cbeg ? p->d_cend : p->d_tslot + 1, p->dtype, p->d_ybuf,
                                    (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, est, st);
@@ -872,9 +873,10 @@ int plan_combine(tn_plan *p, hipStream_t st, double *stats, double *samples_out)
     rc = launch_m1_combine_big(p->n_nets, p->d_tslot, p->d_pairs, p->d_pair0, p->n_pairs, p->dtype, p->d_ybuf,
                                (int64_t)p->h_slots.size(), p->S, 0, p->S, p->log2m, p->d_tw, p->d_cbuf,
                                p->d_partial, est, st);
-  else if (p->flags & TN_FLAG_DFT_BF16)
+  else if (p->flags & (TN_FLAG_DFT_BF16 | TN_FLAG_DFT_FP8))
     rc = launch_m1_combine_dft32(p->d_nets, p->n_nets, p->d_tslot, p->d_tslot + 1, p->d_ybuf,
-                                 (int64_t)p->h_slots.size(), p->S, 0, p->S, est, st);
+                                 (int64_t)p->h_slots.size(), p->S, 0, p->S, est, (p->flags & TN_FLAG_DFT_FP8) != 0,
+                                 st);
   else
     rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->d_tslot + 1, p->dtype, p->d_ybuf,
                            (int64_t)p->h_slots.size(), p->S, 0, p->S, p->log2m, p->d_tw, est, st);

@@ -153,11 +153,11 @@ int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, 
                       int dtype, const void *ybuf, int64_t n_slots, int64_t samples,
                       int64_t sample0, int64_t S, int log2m, const void *twiddles,
                       double *est, hipStream_t st);
-// The combine with its 1024-point DFTs on the BF16 matrix cores (dft.hip;
-// FP32 sketches, m = 1024 only).
+// The combine with its 1024-point DFTs on the BF16 matrix cores, or with fp8
+// on the FP8 ones (dft.hip; FP32 sketches, m = 1024 only).
 int launch_m1_combine_dft32(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend,
                             const void *ybuf, int64_t n_slots, int64_t samples, int64_t sample0, int64_t S,
-                            double *est, hipStream_t st);
+                            double *est, bool fp8, hipStream_t st);
 // The two-pass combine (the m-point FFT does not fit in LDS).  pairs: n_pairs x
 // (tensor a, tensor b or -1), the tensors of each network two by two; pair0:
 // n_nets + 1 offsets into pairs.  cbuf: samples x n_pairs x m complex (A);
