@@ -76,3 +76,29 @@ def test_rejects_other_sizes(T):
     with pytest.raises(T.TNError) as e:
         T.Plan([spec], T.TN_CYCLIC, 1024, 4, 1, flags=T.TN_FLAG_DFT_BF16 | T.TN_FLAG_PERSISTENT)
     assert e.value.code == T.TN_ERR_UNSUPPORTED
+
+
+def test_batched_bench_shape(T, orc):
+    """The benchmark's default configuration: all 4096 networks of the batch in
+    one autotuned plan with TN_FLAG_DFT_BF16, S = 16 (two sample chunks);
+    sampled networks and samples, including the last of each chunk, against
+    the oracle within the bar."""
+    import torch
+    nets = W.random_batch(count=4096, seed=4)
+    specs, views = [], []
+    for n in nets:
+        ts = [torch.from_numpy(np.ascontiguousarray(x)).to("cuda", torch.float32) for x in n.data]
+        specs.append(T.NetworkSpec.from_network(n, ts))
+        views.append((n, ts))
+    plan = T.Plan(specs, T.TN_CYCLIC, 1024, 16, 0, flags=T.TN_FLAG_AUTOTUNE | T.TN_FLAG_DFT_BF16)
+    stats, got = run(plan)
+    worst = 0.0
+    for j in (0, 1, 2047, 4095):
+        n, ts = views[j]
+        v = n.with_data([t.double().cpu().numpy() for t in ts])
+        ref, scale = oracle_samples(orc, v, 1024, j, [0, 7, 8, 15])
+        rel = np.abs(got[j, [0, 7, 8, 15]] - ref) / scale
+        assert np.all(rel <= BAR), (j, rel.max())
+        worst = max(worst, rel.max())
+    assert np.allclose(stats[:, 0], got.mean(axis=1), rtol=1e-12, atol=0)
+    print(f"bench shape: max |error| / scale = {worst:.3e} (bar {BAR:.3e})")
