@@ -488,12 +488,14 @@ int tn_mlp_load(const char *path, tn_mlp **out, double *meta, int32_t max_meta, 
   *out = nullptr;
   FILE *f = std::fopen(path, "rb");
   if (!f) return set_error(TN_ERR_ARG, "cannot open %s", path);
+  const size_t head = 8 + 4 + 4 + 4 + 4 + 8;
+  const size_t largest = head + 64 * 8 + ((size_t)1 << 26) * 4 + 4;  // the largest legal file
   std::vector<unsigned char> buf;
   unsigned char tmp[65536];
   size_t r;
-  while ((r = std::fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + r);
+  while ((r = std::fread(tmp, 1, sizeof(tmp), f)) > 0 && buf.size() <= largest) buf.insert(buf.end(), tmp, tmp + r);
   std::fclose(f);
-  const size_t head = 8 + 4 + 4 + 4 + 4 + 8;
+  if (buf.size() > largest) return set_error(TN_ERR_ARG, "%s is too large for a regressor file", path);
   if (buf.size() < head + 4 || std::memcmp(buf.data(), kMagic, 8) != 0)
     return set_error(TN_ERR_ARG, "%s is not a regressor file", path);
   uint32_t version, crc;

@@ -122,3 +122,26 @@ def test_binding_rejects_bad_buffers(T):
         _device_buffer(torch.zeros(4, dtype=torch.float64), torch.float64, 4, "stats")
     with pytest.raises(ValueError):
         T.median_of_means(torch.zeros(2, 8, dtype=torch.float64), 2)
+
+
+def test_regressor_file_rejections(T, tmp_path):
+    """tn_mlp_load refuses, before any device work, a file that is not a
+    regressor file, one with a bad header, and one larger than the largest
+    legal file (it stops reading there)."""
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a regressor file at all" * 4)
+    with pytest.raises(T.TNError) as e:
+        T.tn_mlp_load(str(junk))
+    assert e.value.code == T.TN_ERR_ARG
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"TNMLP\0\0\1" + (7).to_bytes(4, "little") + bytes(40))
+    with pytest.raises(T.TNError) as e:
+        T.tn_mlp_load(str(bad))
+    assert e.value.code == T.TN_ERR_ARG and "header" in str(e.value)
+    big = tmp_path / "big.bin"
+    with open(big, "wb") as f:
+        f.write(b"TNMLP\0\0\1")
+        f.truncate(300 << 20)  # sparse: no disk blocks
+    with pytest.raises(T.TNError) as e:
+        T.tn_mlp_load(str(big))
+    assert e.value.code == T.TN_ERR_ARG and "too large" in str(e.value)
