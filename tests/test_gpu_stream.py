@@ -139,15 +139,23 @@ def test_triangle_count_from_edge_stream(T, orc):
     assert abs(stats[0, 0] - exact) <= 5 * se, (stats[0, 0], exact, se)
 
 
-@pytest.mark.parametrize("kind", ["chain", "cycle"])
+@pytest.mark.parametrize("kind", ["chain", "cycle", "star"])
 def test_join_size_from_tuple_stream(T, orc, kind):
-    """Cor. 2: Zipf(1.1) relations over domains of 256 streamed tuple by
-    tuple; the acyclic chain query and the cyclic triangle query, m = 4096,
-    S = 256: per-sample parity with the oracle on the frequency tensors and
-    the mean within 5 standard errors of the exact join size."""
-    st = W.join_stream(kind, n=256, tuples=20000, s=1.1, seed=9)
+    """Cor. 2: Zipf(1.1) relations streamed tuple by tuple; the acyclic chain
+    query and the cyclic triangle query over domains of 256, and the star
+    query over 128 whose attribute a joins three relations through a copy
+    tensor (WLOG 1), m = 4096, S = 256: per-sample parity with the oracle on
+    the frequency tensors and the mean within 5 standard errors of the exact
+    join size (for the star, also the plain sum over a, b of
+    f1[a] f2[a] f3[a, b] f4[b], which needs no copy tensor)."""
+    n = 128 if kind == "star" else 256
+    st = W.join_stream(kind, n=n, tuples=20000, s=1.1, seed=9)
     final = st.dense()
     exact = orc.tc_full(final)
+    if kind == "star":
+        f1, f2, f3, f4, C = final.data
+        assert np.count_nonzero(C) == n and np.all(np.einsum("iii->i", C) == 1.0)
+        assert exact == pytest.approx(float((f1 * f2) @ f3 @ f4), rel=1e-12)
     m, S, seed = 4096, 256, 5
     plan, _ = resident(T, st.net, "float32", m, S, seed)
     plan.reset()

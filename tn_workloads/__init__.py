@@ -385,22 +385,34 @@ def join_stream(kind="chain", n=256, tuples=20000, s=1.1, seed=9):
     """Relations as a tuple stream for join-size estimation (Cor. 2): each
     relation is a frequency tensor over its join attributes, and each tuple an
     update +1 of its entry.  kind 'chain': R1(a) R2(a,b) R3(b,c) R4(c) joined
-    on a, b, c (acyclic); 'cycle': R1(a,b) R2(b,c) R3(c,a) (cyclic).  Join keys
+    on a, b, c (acyclic); 'cycle': R1(a,b) R2(b,c) R3(c,a) (cyclic); 'star':
+    R1(a) R2(a) R3(a,b) R4(b), where attribute a joins three relations (a
+    hyperedge): by WLOG 1 a copy tensor C[a, a', a''] = [a = a' = a''] of order
+    3 takes the place of the hyperedge, its three modes contracted with the
+    three a modes; its n diagonal ones lead the stream (tensor 4).  Join keys
     are Zipf(s) over domains of size n.  Returns a Stream."""
     rng = np.random.default_rng([seed, 41])
+    tensor, index, delta = [], [], []
     if kind == "chain":
         net = Network([1, 2, 2, 1], [n] * 6, [(0, 1), (2, 3), (4, 5)], name=f"join_chain{n}")
         arities = [1, 2, 2, 1]
     elif kind == "cycle":
         net = Network([2, 2, 2], [n] * 6, [(1, 2), (3, 4), (5, 0)], name=f"join_cycle{n}")
         arities = [2, 2, 2]
+    elif kind == "star":
+        # modes: R1 0; R2 1; R3 2 (a), 3 (b); R4 4; C 5, 6, 7
+        net = Network([1, 1, 2, 1, 3], [n] * 8, [(0, 5), (1, 6), (2, 7), (3, 4)], name=f"join_star{n}")
+        arities = [1, 1, 2, 1]
+        diag = np.arange(n, dtype=np.int64)
+        tensor.append(np.full(n, 4))
+        index.append(diag * n * n + diag * n + diag)
+        delta.append(np.ones(n))
     else:
         raise ValueError(kind)
-    tensor, index = [], []
     for k, a in enumerate(arities):
         cols = [_zipf_keys(rng, n, tuples, s) for _ in range(a)]
         lin = cols[0] if a == 1 else cols[0] * n + cols[1]
         tensor.append(np.full(tuples, k))
         index.append(lin)
-    return Stream(net, np.concatenate(tensor), np.concatenate(index), np.ones(tuples * len(arities)),
-                  f"{kind}{n}")
+        delta.append(np.ones(tuples))
+    return Stream(net, np.concatenate(tensor), np.concatenate(index), np.concatenate(delta), f"{kind}{n}")
