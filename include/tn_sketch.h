@@ -15,6 +15,13 @@
  * Every mode must take part in exactly one contraction: the estimators cover
  * full TNC (Theorem 1), under WLOG 1 of the Methods section.
  *
+ * Environment: TN_LOG=1 prints each plan's layout, the autotuner's choices,
+ * the size choices of auto-sized plans and the exact contraction's memory peak
+ * on stderr, one "[tn] ..." line each; TN_LOG=2 also every autotuner
+ * candidate and the exact contraction's tree kind.  TN_SCATTER_SB and
+ * TN_SCATTER_BANKS fix the cyclic scatter's samples per pass and accumulator
+ * banks of plans built without TN_FLAG_AUTOTUNE (test overrides).
+ *
  * Estimators:
  *   TN_CYCLIC  -- the first method, for any network (Eq. (1), Algorithm 1):
  *                 edge e draws a count sketch C_u for its first mode u and

@@ -7,6 +7,7 @@
 // device allocation or launch.
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -27,6 +28,21 @@ int set_error(int code, const char *fmt, ...) {
 }
 
 void clear_error() { g_err[0] = '\0'; }
+
+int log_level() {
+  const char *e = std::getenv("TN_LOG");
+  return e ? std::atoi(e) : 0;
+}
+
+void log_msg(int level, const char *fmt, ...) {
+  if (log_level() < level) return;
+  char line[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(line, sizeof(line), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[tn] %s\n", line);
+}
 
 const char *last_error() { return g_err; }
 

@@ -710,6 +710,7 @@ int contract_exact(const tn_network *net, hipStream_t st, double *out) {
       ok = dp_tree(ls, ldim, cap, &trees[(size_t)c]);
     }
     if (!ok) greedy_tree(labs, ldim, &trees[(size_t)c]);
+    log_msg(2, "exact: component %d: %zu tensors, %s tree", c, mb.size(), ok ? "fewest-flop (subset DP)" : "greedy");
   }
   // Dry run: the peak of live device memory.
   {
@@ -732,6 +733,8 @@ int contract_exact(const tn_network *net, hipStream_t st, double *out) {
       DTensor r;
       if ((rc = run_tree(dry, trees[(size_t)c], trees[(size_t)c].root, ts, &memo, &r)) != TN_OK) return rc;
     }
+    log_msg(1, "exact: %d tensors in %d components, peak %.3g GB of device memory (%.3g GB free)", p, n_comp,
+            (double)dry.peak / 1e9, (double)free_b / 1e9);
     if ((double)dry.peak > 0.92 * (double)free_b)
       return set_error(TN_ERR_OOM, "exact contraction needs %.3g GB of device memory at its peak, %.3g GB free",
                        (double)dry.peak / 1e9, (double)free_b / 1e9);

@@ -1483,6 +1483,8 @@ int m2_autotune(tn_plan *p, hipStream_t st) {
     for (const auto &kv : g_m2_tuned)
       if (kv.first == key) {
         apply(kv.second);
+        log_msg(1, "autotune: cached schedule, split target %d, gather target %d", kv.second.first,
+                kv.second.second);
         return TN_OK;
       }
   }
@@ -1510,6 +1512,7 @@ int m2_autotune(tn_plan *p, hipStream_t st) {
         if (rc == TN_OK) (void)hipEventElapsedTime(&ms, e0, e1);
         if (rep > 0) ms_min = std::min(ms_min, ms);
       }
+      if (rc == TN_OK) log_msg(2, "autotune: split target %d, gather target %d: %.4f ms", split, gather, (double)ms_min);
       if (rc == TN_OK && ms_min < best_ms) {
         best_ms = ms_min;
         best = {split, gather};
@@ -1521,6 +1524,8 @@ int m2_autotune(tn_plan *p, hipStream_t st) {
   p->flags = saved_flags;
   apply(best);
   if (rc != TN_OK) return rc;
+  log_msg(1, "autotune: split target %d, gather target %d (%.4f ms for %lld samples)", best.first, best.second,
+          (double)best_ms, (long long)n);
   std::lock_guard<std::mutex> lk(g_m2_tuned_mu);
   g_m2_tuned.push_back({key, best});
   return TN_OK;

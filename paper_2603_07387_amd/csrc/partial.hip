@@ -332,6 +332,7 @@ extern "C" int tn_partial_plan(const tn_network *net, int64_t m, int64_t samples
     plan_release(p);
     return rc;
   }
+  log_plan(p);
   *out = plan.release();
   return TN_OK;
 }

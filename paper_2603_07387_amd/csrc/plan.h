@@ -165,6 +165,7 @@ int m1_check_m(tn_plan *p);
 int add_tensor_slots(tn_plan *p, int32_t gtensor, int32_t mode0, int q, const int64_t *dims, int64_t size,
                      int net, int k);
 int m1_layout(tn_plan *p, const std::vector<NetCheck> *chk);
+void log_plan(const tn_plan *p);
 int plan_common(tn_plan *p);
 int plan_alloc_tail(tn_plan *p);
 // resident sketches (TN_FLAG_RESIDENT)

@@ -476,7 +476,10 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
       for (const auto &kv : g_tuned)
         if (kv.first == key) hit = kv.second;
     }
-    if (hit.first > 0) return apply(hit.first, hit.second);
+    if (hit.first > 0) {
+      log_msg(1, "autotune: cached schedule, samples per pass %d, banks %d", hit.first, hit.second);
+      return apply(hit.first, hit.second);
+    }
   }
   const int64_t n = std::min(p->fused ? p->fused_chunk_cap : p->chunk, p->S);
   const int32_t *tables = nullptr;
@@ -562,6 +565,7 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
       if (rc != TN_OK) break;
       // per sample of the chunk, so that candidates with different chunks compare
       const float per = ms_min / (float)(p->fused ? std::min(n, p->fused_chunk) : n);
+      log_msg(2, "autotune: samples per pass %d, banks %d: %.4f ms per sample", sb, banks, (double)per);
       if (per < best_ms) { best_ms = per; best = {sb, banks}; }
     }
     if (rc != TN_OK) break;
@@ -570,6 +574,8 @@ int m1_autotune(tn_plan *p, hipStream_t st) {
   (void)hipEventDestroy(e1);
   if (rc != TN_OK) return rc;
   if ((rc = apply(best.first, best.second)) != TN_OK) return rc;
+  log_msg(1, "autotune: samples per pass %d, banks %d (%.4f ms per sample)", best.first, best.second,
+          (double)best_ms);
   {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
     g_tuned.push_back({key, best});
@@ -680,8 +686,27 @@ int plan_build(tn_plan *p, const tn_network *nets, int n_nets, int method, int64
   if (rc != TN_OK) return rc;
   rc = (method == TN_CYCLIC) ? m1_build(p, nets, chk) : m2_build(p, nets, chk);
   if (rc == TN_OK) rc = plan_alloc_tail(p);
-  if (rc != TN_OK) plan_release(p);
+  if (rc != TN_OK) {
+    plan_release(p);
+    return rc;
+  }
+  log_plan(p);
   return rc;
+}
+
+void log_plan(const tn_plan *p) {
+  if (log_level() < 1) return;
+  if (p->method == TN_CYCLIC)
+    log_msg(1,
+            "plan: cyclic, %d networks (%d outputs), %d tensors, %zu slots, m %lld, S %lld, chunk %lld, %s, "
+            "samples per pass %d, banks %d, flags 0x%x",
+            p->partial ? 1 : p->n_nets, p->n_nets, p->n_tensors, p->h_slots.size(), (long long)p->m,
+            (long long)p->S, (long long)p->chunk,
+            p->fused ? "persistent kernel" : p->two_pass ? "two-pass combine" : "in-LDS combine",
+            p->fused ? p->fused_sb : p->sb, p->fused ? p->fused_banks : p->banks, p->flags);
+  else
+    log_msg(1, "plan: acyclic, %d networks, %d tensors, m %lld, S %lld, chunk %lld, root %d, flags 0x%x", p->n_nets,
+            p->n_tensors, (long long)p->m, (long long)p->S, (long long)p->chunk, p->root, p->flags);
 }
 
 // Device and its LDS limit.

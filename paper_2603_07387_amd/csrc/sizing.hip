@@ -381,6 +381,9 @@ int auto_size(const tn_network *nets, int n_nets, int method, uint32_t flags, ui
       if (v < bv) { bv = v; bm = L[i]; }
     }
   }
+  log_msg(1, "size: %s variance, eps %g, delta %g, %d networks: m %lld, S %lld%s",
+          mode == TN_SIZE_LEARNED ? "learned" : mode == TN_SIZE_PILOT ? "pilot" : "bound", eps, delta, n_nets,
+          (long long)bm, (long long)bS, best_w < 0.0 ? " (target out of reach: least variance)" : "");
   *m_out = bm;
   *S_out = bS;
   return TN_OK;

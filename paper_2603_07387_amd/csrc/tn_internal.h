@@ -15,6 +15,11 @@ namespace tn {
 // Error reporting (thread-local text behind tn_last_error()).
 // ---------------------------------------------------------------------------
 int set_error(int code, const char *fmt, ...);
+// Diagnostics on stderr, one "[tn] ..." line per call, printed when the
+// environment variable TN_LOG is at least `level` (1: plan decisions and
+// choices; 2: also every autotuner candidate).  Read at each call.
+int log_level();
+void log_msg(int level, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
 
 #define TN_HIP_CHECK(call)                                                        \

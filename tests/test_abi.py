@@ -145,3 +145,25 @@ def test_regressor_file_rejections(T, tmp_path):
     with pytest.raises(T.TNError) as e:
         T.tn_mlp_load(str(big))
     assert e.value.code == T.TN_ERR_ARG and "too large" in str(e.value)
+
+
+def test_tn_log_levels(T, capfd, monkeypatch):
+    """TN_LOG=1 prints the size choice of an auto-sized plan (made on the host,
+    before any device work) as one "[tn] size: ..." line on stderr; unset, the
+    library prints nothing."""
+    spec = _spec(T, W.triangle(16))
+
+    def attempt():
+        try:
+            h = T.tn_sketch_plan([spec], 1, 0, 0, 0)
+            T.tn_plan_destroy(h)
+        except T.TNError:
+            pass  # no device here: the plan stops after choosing its size
+
+    monkeypatch.delenv("TN_LOG", raising=False)
+    attempt()
+    assert "[tn]" not in capfd.readouterr().err
+    monkeypatch.setenv("TN_LOG", "1")
+    attempt()
+    err = capfd.readouterr().err
+    assert "[tn] size: bound variance, eps 0.01, delta 0.25, 1 networks: m " in err, err

@@ -551,3 +551,23 @@ def test_tt_ladder_full_size(T, orc):
     small = W.tt_ladder(cores=4, bond=3, phys=2, seed=5, dtype=np.float64)
     spec = T.NetworkSpec.from_network(small, dev(small, "float64"))
     assert T.tn_contract_exact(spec) == pytest.approx(orc.tc_full(small), rel=1e-12, abs=1e-14)
+
+
+def test_tn_log_plan_and_autotune(T, orc, capfd, monkeypatch):
+    """TN_LOG=2: a plan prints its layout and the autotuner each candidate and
+    its choice (or the cached schedule) on stderr, acyclic plans likewise."""
+    monkeypatch.setenv("TN_LOG", "2")
+    nets = [W.ring(5, 24, seed=77), W.triangle(24, seed=78)]
+    plan, _ = make_plan(T, nets, "float32", 512, 24, 3, flags=T.TN_FLAG_AUTOTUNE)
+    run(plan)
+    err = capfd.readouterr().err
+    assert "[tn] plan: cyclic, 2 networks" in err, err
+    assert "[tn] autotune: " in err, err
+    import torch
+    net = W.tt_caterpillar(cores=4, bond=8, phys=4, seed=79)
+    ts = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in net.data]
+    p2 = T.Plan([T.NetworkSpec.from_network(net, ts)], T.TN_ACYCLIC, 256, 128, 1, flags=T.TN_FLAG_AUTOTUNE)
+    p2.estimate()
+    torch.cuda.synchronize()
+    err = capfd.readouterr().err
+    assert "[tn] plan: acyclic, 1 networks" in err and "[tn] autotune: split target" in err, err
