@@ -163,3 +163,27 @@ def test_torus_d16_uniform_two_presentations(T):
     print(f"torus 4x4 D=16 uniform: {z1:.17g} / {z2:.17g}")
     assert z1 > 0 and z2 == pytest.approx(z1, rel=1e-12)
     _free_cache()
+
+
+def test_out_of_memory_refused_before_allocation(T):
+    """The 4 x 4 torus at bond 24 needs 24^8-entry intermediates (0.9 TB in
+    FP64): the dry run of the contraction tree finds the peak above the free
+    device memory and the call returns TN_ERR_OOM before allocating any of it.
+    A plan whose per-sample estimates would take 512 GB is refused with
+    TN_ERR_OOM too (the failed allocation is returned, the rest released)."""
+    import torch
+    _free_cache()
+    net = W.torus(L=4, D=24, seed=4)
+    ts = [torch.from_numpy(x).cuda() for x in net.data]
+    with pytest.raises(T.TNError) as e:
+        T.tn_contract_exact(T.NetworkSpec.from_network(net, ts))
+    assert e.value.code == T.TN_ERR_OOM and "GB of device memory" in str(e.value), str(e.value)
+    tri = W.triangle(8, seed=1, dtype=np.float32)
+    spec = T.NetworkSpec.from_network(tri, [torch.from_numpy(x).cuda() for x in tri.data])
+    with pytest.raises(T.TNError) as e:
+        T.Plan([spec], T.TN_CYCLIC, 64, 1 << 36, 1)
+    assert e.value.code == T.TN_ERR_OOM, str(e.value)
+    # the device is still usable
+    plan = T.Plan([spec], T.TN_CYCLIC, 64, 16, 1)
+    plan.estimate()
+    torch.cuda.synchronize()
