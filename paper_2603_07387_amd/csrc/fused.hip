@@ -88,7 +88,7 @@ __global__ __launch_bounds__(256) void m1_fused_kernel(
         for (int si = tslot[t]; si < tslot[t + 1]; ++si) {
           const ScatterSlot sl = slots[si];
           scatter_slot<T, SB, BANKS, 256>(sl, modes, data, tab0, W, nsb, LOG2M, acc + side * M, 16u * M, kSignbit,
-                              tabs, tabs + SB * sl.L, s_max, fs[side]);
+                              tabs, s_max, fs[side]);
         }
       }
       const double ia = ldexp(1.0, -fs[0].scale);

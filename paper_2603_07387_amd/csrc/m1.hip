@@ -28,6 +28,12 @@ namespace {
 using namespace m1dev;
 
 
+// Waves per SIMD the register allocation must allow: four (two blocks per CU)
+// for the 512-thread FP32 blocks whose loop keeps 8 loads in flight (their
+// LDS leaves room for two blocks at m = 1024); no constraint otherwise.
+template <typename T, int SB, int NT>
+constexpr int kScatterWavesPerEU = (NT == 512 && sizeof(T) == 4 && SB * 4 <= 16) ? 4 : 1;
+
 // One block streams one slot and accumulates the sketches of SB samples (see
 // scatter_slot), then writes them out as floating point.
 // Blocks of 256 threads with one bank, 512 with two (twice the accumulator LDS
@@ -41,7 +47,7 @@ using namespace m1dev;
 // and, with bound_out, records the power-of-two bound it ends with.
 // Sample batch blockIdx.y + y0 of the launch's samples.
 template <typename T, typename A, int SB, int BANKS, bool RANGED = false, int NT = 256 * BANKS>
-__global__ __launch_bounds__(NT) void m1_scatter_kernel(
+__global__ __launch_bounds__(NT, (kScatterWavesPerEU<T, SB, NT>)) void m1_scatter_kernel(
     const ScatterSlot *__restrict__ slots, const ModeDesc *__restrict__ modes,
     const void *const *__restrict__ data, const int32_t *__restrict__ tables, int64_t W,
     int64_t samples, int log2m, int log2acc, int64_t n_slots, A *__restrict__ ybuf,
@@ -62,10 +68,8 @@ __global__ __launch_bounds__(NT) void m1_scatter_kernel(
   const size_t acc_end = (acc_bytes + 15) & ~(size_t)15;
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
   unsigned long long *s_max = reinterpret_cast<unsigned long long *>(smem + acc_end);  // [2]
-  uint32_t *colt = reinterpret_cast<uint32_t *>(smem + acc_end + 16);                  // [SB][L]
-  uint32_t *rowt = colt + SB * sl.L;                                                   // [SB][rows]
-  for (int i = tid; i < (int)(acc_bytes / 8); i += NT) acc[i] = 0ull;
-  if (tid < 2) s_max[tid] = 0ull;
+  uint32_t *tabs = reinterpret_cast<uint32_t *>(smem + acc_end + 16);  // column and row tables
+  if (tid < 2) s_max[tid] = 0ull;  // the accumulators are cleared by scatter_slot
   const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
   FixedScale fs;
   fs.lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
@@ -81,7 +85,8 @@ __global__ __launch_bounds__(NT) void m1_scatter_kernel(
     fs.known = true;
   }
   scatter_slot<T, SB, BANKS, NT, RANGED>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * ma, signbit,
-                                         colt, rowt, s_max, fs, blockIdx.z, RANGED ? log2acc : -1);
+                                         tabs, s_max, fs, blockIdx.z, RANGED ? log2acc : -1,
+                                         reinterpret_cast<uint32_t *>(acc), (uint32_t)(acc_bytes / 4));
   if (bound_out != nullptr && tid == 0 && blockIdx.y == 0 && blockIdx.z == 0) bound_out[blockIdx.x] = fs.bound;
   const unsigned long long *neg = acc + signbit / 8;
   const int lga = RANGED ? log2acc : log2m;

@@ -120,11 +120,15 @@ __host__ __device__ constexpr size_t sign_bank_bytes(int sb, uint32_t m) {
 // of the two signs in the signbit position (the bucket sum stays below 16 m),
 // and masking it with 8(m - 1) | signbit leaves the byte offset of the target
 // word: no sign test and no negation per term.
-// Builds the slot's packed row and column tables in rowt / colt (LDS, SB x
-// rows and SB x L words), then streams the slot once from HBM with 16-byte
+// Builds the slot's packed column and row tables in `tabs` (LDS, SB (L +
+// kColPad + rows) + 1 words), then streams the slot once from HBM with 16-byte
 // loads.  s_max (2 words of LDS) holds the running maximum; both it and fs
 // carry over between calls that feed the same sketches.  All NT threads of
 // the block call it; it starts and ends with a barrier.
+// fresh (optional): the accumulators, fresh_words 4-byte words, not yet
+// cleared; the column tables are then built from the modes' hash words staged
+// there, and the accumulators are cleared before the scatter.  Without it the
+// caller clears them.
 // RANGED (one bank): the LDS holds only the 2^log2acc buckets starting at
 // bucket rsel * 2^log2acc of each sketch; terms outside that range are
 // dropped.  Every range sees the same terms in the same order, so all ranges
@@ -134,37 +138,111 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
                                              const void *const *__restrict__ data,
                                              const int32_t *__restrict__ tables, int64_t W, int nsb,
                                              int log2m, unsigned long long *acc, uint32_t sbytes,
-                                             uint32_t signbit, uint32_t *colt, uint32_t *rowt,
+                                             uint32_t signbit, uint32_t *tabs,
                                              unsigned long long *s_max, FixedScale &fs, uint32_t rsel = 0,
-                                             int log2acc = -1) {
+                                             int log2acc = -1, uint32_t *fresh = nullptr,
+                                             uint32_t fresh_words = 0) {
   static_assert(!RANGED || BANKS == 1, "bucket ranges use one bank");
   if (log2acc < 0) log2acc = log2m;
   const uint32_t rshift = 3u + (uint32_t)log2acc;  // byte offset >> rshift = range index
   const int tid = threadIdx.x;
   const uint32_t m = 1u << log2m, mask = m - 1;
   const int L = sl.L, rows = sl.rows;
+  constexpr int VEC = 16 / (int)sizeof(T);  // entries per 16-byte load
+  // Column tables first, sample s's at colt + s Lp: its L words, then the
+  // first VEC - 1 columns again (word L + j holds column j mod L), so a
+  // vector that runs on into the next row reads its VEC column words without
+  // a wrap test.  Row tables after them, sample s's at rowt + s rows, and one
+  // more word (a vector in the last row reads the word after that row).
+  const int Lp = L + kColPad, Lb = L + VEC - 1;
+  static_assert(VEC - 1 <= kColPad, "column table padding");
+  uint32_t *colt = tabs;
+  uint32_t *rowt = tabs + SB * Lp;
   auto to_offset = [signbit](uint32_t v) {
     (void)signbit;  // unused with one bank
     if constexpr (BANKS == 2) return ((v & ~kSignBit) << 3) + ((v & kSignBit) ? signbit : 0u);
     else return ((v & ~kSignBit) << 3) | (v & kSignBit);  // sign stays in bit 31
   };
   __syncthreads();  // earlier readers of the tables are done
-  for (int i = tid; i < nsb * L; i += NT) {
-    const int s = i / L, c = i - s * L;
-    colt[s * L + c] = to_offset(combine_modes(tables + s * W, modes, sl.mode0 + sl.split,
-                                              sl.mode0 + sl.q - 1, c, m, mask));
+  const int uc0 = sl.mode0 + sl.split, uc1 = sl.mode0 + sl.q - 1;  // column modes
+  int qc = 0;  // their hash words per sample
+  for (int u = uc0; u <= uc1; ++u) qc += modes[u].n;
+  if (fresh != nullptr && (uint32_t)(nsb * qc) <= fresh_words) {
+    // The column modes' hash words of the nsb samples, complement applied,
+    // staged in the (not yet cleared) accumulator LDS: sample s, mode u,
+    // index d at fresh[s qc + off_u + d], modes in order.  One global read
+    // per word instead of one per (column, mode).
+    for (int i = tid; i < nsb * qc; i += NT) {
+      const int s = i / qc;
+      int d = i - s * qc, u = uc0;
+      while (d >= modes[u].n) d -= modes[u++].n;
+      const ModeDesc md = modes[u];
+      const uint32_t v = (uint32_t)tables[s * W + md.table_off + d];
+      uint32_t h = v & ~kSignBit;
+      if (md.comp) h = (m - h) & mask;
+      fresh[i] = h | (v & kSignBit);
+    }
+    __syncthreads();
+    // Column c's word per sample: the digits of c mod L, last mode fastest,
+    // found once for all samples.
+    for (int c = tid; c < Lb; c += NT) {
+      uint32_t idx = (uint32_t)(c < L ? c : c % L), w[SB];
+#pragma unroll
+      for (int s = 0; s < SB; ++s) w[s] = 0;
+      int off = qc;
+      for (int u = uc1; u >= uc0; --u) {
+        const uint32_t n = (uint32_t)modes[u].n;
+        off -= (int)n;
+        const uint32_t d = idx % n;
+        idx /= n;
+#pragma unroll
+        for (int s = 0; s < SB; ++s)
+          if (s < nsb) {
+            const uint32_t v = fresh[s * qc + off + d];
+            w[s] = (((w[s] & ~kSignBit) + (v & ~kSignBit)) & mask) | ((w[s] ^ v) & kSignBit);
+          }
+      }
+#pragma unroll
+      for (int s = 0; s < SB; ++s)
+        if (s < nsb) colt[s * Lp + c] = to_offset(w[s]);
+    }
+  } else {
+    for (int i = tid; i < nsb * Lb; i += NT) {
+      const int s = i / Lb, c = i - s * Lb;
+      colt[s * Lp + c] = to_offset(combine_modes(tables + s * W, modes, uc0, uc1, c < L ? c : c % L, m, mask));
+    }
   }
   for (int i = tid; i < nsb * rows; i += NT) {
     const int s = i / rows, r = i - s * rows;
-    rowt[s * rows + r] = to_offset(combine_modes(tables + s * W, modes, sl.mode0,
-                                                 sl.mode0 + sl.split - 1,
+    rowt[s * rows + r] = to_offset(combine_modes(tables + s * W, modes, sl.mode0, sl.mode0 + sl.split - 1,
                                                  (uint32_t)(sl.row0 + r), m, mask));
   }
   __syncthreads();
+  if (fresh != nullptr) {  // clear the accumulators (they held the staged words)
+    unsigned long long *f8 = reinterpret_cast<unsigned long long *>(fresh);
+    for (uint32_t i = tid; i < fresh_words / 2; i += NT) f8[i] = 0ull;
+    __syncthreads();
+  }
   const uint32_t amask = (mask << 3) | (BANKS == 2 ? signbit : 0u);
   char *acc8 = reinterpret_cast<char *>(acc);
+  // The slot's entries as 16-byte vectors: from the start when every row is a
+  // whole number of vectors and the slot starts 16-byte aligned (vec), else
+  // from the first aligned vector (the entries before it and after the last
+  // whole vector are read singly).
+  using V = typename Vec16<T>::type;
+  // 16-byte loads in flight per thread: 8 in the 512-thread blocks (two per CU,
+  // registers to spare; half the barriers per entry), else 4; 4 in the
+  // unaligned loop (its tables take the registers)
+  constexpr int UNROLL = NT == 512 && SB * VEC <= 16 ? 8 : 4;
+  constexpr int UNW = 4;
   const T *X = reinterpret_cast<const T *>(data[sl.tensor]) + sl.row0 * (int64_t)L;
   const uint32_t N = (uint32_t)rows * (uint32_t)L;
+  const bool vec = (L % VEC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+  const uint32_t head =
+      vec ? 0u : min(N, ((16u - ((uint32_t)reinterpret_cast<uintptr_t>(X) & 15u)) & 15u) / (uint32_t)sizeof(T));
+  const uint32_t NV = (N - head) / VEC;
+  const V __attribute__((address_space(1))) *Xv =
+      (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X + head);
 
   // Block-wide running max of |x| (double-buffered so the read of one
   // iteration cannot race with the next iteration's update), then a rescale
@@ -226,32 +304,23 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
     const long long v = to_fixed(x), nv = -v;
     uint32_t hv[SB], lv[SB];
 #pragma unroll
-    for (int s = 0; s < SB; ++s) { hv[s] = rowt[s * rows + r]; lv[s] = colt[s * L + c]; }
+    for (int s = 0; s < SB; ++s) { hv[s] = rowt[s * rows + r]; lv[s] = colt[s * Lp + c]; }
 #pragma unroll
     for (int s = 0; s < SB; ++s)
       if (s < nsb) add_fixed(s, hv[s], lv[s], v, nv);
   };
-  constexpr int VEC = 16 / (int)sizeof(T);   // entries per 16-byte load
   // Row and column entries of every sample for VEC consecutive entries of one
   // row (all reads issued before any add, so one LDS wait covers them).
   auto read_tabs = [&](uint32_t r, uint32_t c, uint32_t *hv, uint32_t (*lv)[VEC]) {
 #pragma unroll
     for (int s = 0; s < SB; ++s) {
       hv[s] = rowt[s * rows + r];
-      load_cols<VEC>(colt + s * L + c, lv[s]);
+      load_cols<VEC>(colt + s * Lp + c, lv[s]);
     }
   };
-  // 16-byte loads in flight per thread: 8 in the 512-thread blocks (two per CU,
-  // registers to spare; half the barriers per entry), else 4
-  constexpr int UNROLL = NT == 512 && SB * VEC <= 16 ? 8 : 4;
-  const bool vec = (L % VEC == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
   if (vec) {
     // Rows are multiples of VEC long and the slot starts 16-byte aligned, so
     // the VEC entries of one load share a row.
-    using V = typename Vec16<T>::type;
-    const V __attribute__((address_space(1))) *Xv =
-        (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X);
-    const uint32_t NV = N / VEC;
     // Unconditional loads (index clamped into the slot) keep all UNROLL loads
     // in flight; out-of-range lanes are masked when the values are used.
     // Blocks of 512 or more threads (few blocks per CU: their LDS is large)
@@ -271,7 +340,7 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
         uint32_t lvf[SB][VEC];
         if constexpr (FIXED) {
 #pragma unroll
-          for (int s = 0; s < SB; ++s) load_cols<VEC>(colt + s * L + ((uint32_t)tid * VEC) % (uint32_t)L, lvf[s]);
+          for (int s = 0; s < SB; ++s) load_cols<VEC>(colt + s * Lp + ((uint32_t)tid * VEC) % (uint32_t)L, lvf[s]);
         }
         V buf[UNROLL], nxt[UNROLL];
 #pragma unroll
@@ -400,9 +469,7 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
     // are read singly, one per thread, first.
     const T __attribute__((address_space(1))) *Xg =
         (const T __attribute__((address_space(1))) *)X;
-    const uint32_t head =
-        min(N, ((16u - ((uint32_t)reinterpret_cast<uintptr_t>(X) & 15u)) & 15u) / (uint32_t)sizeof(T));
-    const uint32_t NV = (N - head) / VEC, body = head + NV * VEC;
+    const uint32_t body = head + NV * VEC;
     {
       const uint32_t singles = head + (N - body);  // < 2 VEC <= NT
       const uint32_t e = (uint32_t)tid < head ? (uint32_t)tid : body + ((uint32_t)tid - head);
@@ -415,45 +482,73 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
       }
     }
     if (NV > 0) {  // uniform over the block
-      using V = typename Vec16<T>::type;
-      const V __attribute__((address_space(1))) *Xv =
-          (const V __attribute__((address_space(1))) *)reinterpret_cast<const V *>(X + head);
       constexpr bool PREFETCH = NT >= 512;
-      V buf[UNROLL], nxt[UNROLL];
+      V buf[UNW], nxt[UNW];
       if constexpr (PREFETCH) {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
+        for (int u = 0; u < UNW; ++u) nxt[u] = Xv[min((uint32_t)(u * NT + tid), NV - 1)];
       }
-      for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNROLL) {
+      for (uint32_t v0 = 0; v0 < NV; v0 += NT * UNW) {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
+        for (int u = 0; u < UNW; ++u) buf[u] = PREFETCH ? nxt[u] : Xv[min(v0 + u * NT + tid, NV - 1)];
         if (!fs.known) {  // running maximum of this load round (uniform over the block)
           double lmax = 0.0;
 #pragma unroll
-          for (int u = 0; u < UNROLL; ++u) {
+          for (int u = 0; u < UNW; ++u) {
             const T *xs = reinterpret_cast<const T *>(&buf[u]);
 #pragma unroll
             for (int i = 0; i < VEC; ++i) lmax = fmax(lmax, fabs((double)to_acc_any(xs[i])));
           }
           update_scale(lmax);
         }
-        if (PREFETCH && v0 + NT * UNROLL < NV) {  // uniform over the block
+        if (PREFETCH && v0 + NT * UNW < NV) {  // uniform over the block
 #pragma unroll
-          for (int u = 0; u < UNROLL; ++u) nxt[u] = Xv[min(v0 + (u + UNROLL) * NT + tid, NV - 1)];
+          for (int u = 0; u < UNW; ++u) nxt[u] = Xv[min(v0 + (u + UNW) * NT + tid, NV - 1)];
         }
+        if (L >= VEC) {  // uniform over the block: a vector spans at most two rows
+          // Per sample the row words of the vector's row and of the next one
+          // and its VEC column words from the wrapped table, all read before
+          // the vector's adds; entry i takes the next row's word when column
+          // c + i passes the row's end.
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-          if (v0 + u * NT + tid < NV) {
-            const uint32_t e = head + (v0 + u * NT + tid) * VEC;
-            uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
-            uint32_t c = e - r * (uint32_t)L;
-            const T *xs = reinterpret_cast<const T *>(&buf[u]);
+          for (int u = 0; u < UNW; ++u) {
+            if (v0 + u * NT + tid < NV) {
+              const uint32_t e = head + (v0 + u * NT + tid) * VEC;
+              const uint32_t r = __umulhi(e, sl.magic), c = e - r * (uint32_t)L;
+              uint32_t h0[SB], h1[SB], lw[SB][VEC];
 #pragma unroll
-            for (int i = 0; i < VEC; ++i) {
-              scatter_one((double)to_acc_any(xs[i]), r, c);
-              if (++c == (uint32_t)L) {  // the vector runs on into the next row
-                c = 0;
-                ++r;
+              for (int s = 0; s < SB; ++s) {
+                h0[s] = rowt[s * rows + r];
+                h1[s] = rowt[s * rows + r + 1];
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) lw[s][i] = colt[s * Lp + c + i];
+              }
+              const T *xs = reinterpret_cast<const T *>(&buf[u]);
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) {
+                const long long q = to_fixed((double)to_acc_any(xs[i]));
+                const bool same = c + i < (uint32_t)L;
+#pragma unroll
+                for (int s = 0; s < SB; ++s)
+                  if (s < nsb) add_fixed(s, same ? h0[s] : h1[s], lw[s][i], q, -q);
+              }
+            }
+          }
+        } else {  // rows shorter than a vector
+#pragma unroll
+          for (int u = 0; u < UNW; ++u) {
+            if (v0 + u * NT + tid < NV) {
+              const uint32_t e = head + (v0 + u * NT + tid) * VEC;
+              uint32_t r = (L == 1) ? e : __umulhi(e, sl.magic);
+              uint32_t c = e - r * (uint32_t)L;
+              const T *xs = reinterpret_cast<const T *>(&buf[u]);
+#pragma unroll
+              for (int i = 0; i < VEC; ++i) {
+                scatter_one((double)to_acc_any(xs[i]), r, c);
+                if (++c == (uint32_t)L) {  // the vector runs on into the next row
+                  c = 0;
+                  ++r;
+                }
               }
             }
           }

@@ -198,7 +198,7 @@ int m1_layout(tn_plan *p, const std::vector<NetCheck> *chkp) {
   // else one.
   size_t worst_cols_rows = 0;
   for (const ScatterSlot &sl : p->h_slots)
-    worst_cols_rows = std::max(worst_cols_rows, (size_t)(sl.L + sl.rows));
+    worst_cols_rows = std::max(worst_cols_rows, (size_t)(sl.L + kColPad + sl.rows + 1));
   // 64-bit fixed-point accumulators (two banks of 8-byte words per sample)
   // plus packed tables.  (+64: the accumulator block is padded to 16 bytes and
   // the kernel keeps a 16-byte running maximum in static LDS.)

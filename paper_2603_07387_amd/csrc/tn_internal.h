@@ -78,6 +78,7 @@ struct NetDesc {
 
 // Limits of the cyclic scatter.
 constexpr int kMaxCols = 1024;          // columns per slot (packed tables in LDS)
+constexpr int kColPad = 8;              // words after each sample's column table (wrapped copy of its first columns)
 constexpr int kMaxSlotEntries = 1 << 16;  // entries per scatter block
 constexpr int kMaxLog2M1 = 16;          // m <= 65536
 constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
@@ -133,7 +134,7 @@ struct M1FusedLaunch {
   int64_t chunk;              // samples in this launch
   int64_t sample0;
   int64_t S;
-  int32_t worst;              // max over slots of rows + L
+  int32_t worst;              // table words per sample: max over slots of L + kColPad + rows + 1
   int sb;                     // samples per item (1, 2, 4)
   int banks;                  // accumulator banks per sketch (1 or 2, see the slot scatter)
   int log2m;
