@@ -37,7 +37,9 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
                                                                const int32_t *__restrict__ tbeg,
                                                                const int32_t *__restrict__ tend,
                                                                const float *__restrict__ ybuf, int64_t n_slots,
-                                                               int64_t sample0, int64_t S, double *__restrict__ est) {
+                                                               int64_t sample0, int64_t S,
+                                                               const float2 *__restrict__ tw,
+                                                               double *__restrict__ est) {
   constexpr int M = 1024;
   __shared__ __align__(16) __bf16 yT[32 * kYStr];      // yT[b2][b1] = y[32 b1 + b2]
   __shared__ __align__(16) __bf16 bR[32 * kYStr];      // B[j1][b2], real part
@@ -51,39 +53,46 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
   const int ti = w >> 1, tj = w & 1;
   const int l16 = lane & 15, g = lane >> 4;  // operand lane (row or column, k group)
 
-  // Constant operands.  Step 1's A operand: F[16 ti + l16][8 g + e]; step 3's
-  // B operand: F[8 g + e][16 tj + l16].  F is symmetric.
-  dbf16x8 fr1, fi1, fr3, fi3;
+  // Constant operands, read from the plan's half table of 1024-point twiddles
+  // (tw[j] = w1024^j for j < 512; w1024^(j + 512) = -tw[j]): w32^k = w1024^(32 k).
+  // Step 1's A operand: F[16 ti + l16][8 g + e]; step 3's B operand:
+  // F[8 g + e][16 tj + l16].  F is symmetric.
+  auto w1024 = [&](int j) {
+    j &= M - 1;
+    const float2 t = tw[j & (M / 2 - 1)];
+    return j < M / 2 ? t : make_float2(-t.x, -t.y);
+  };
+  dbf16x8 fr1, fi1, fr3, fi3, nfi3;  // nfi3 = -fi3 (for the real part of step 3)
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    float sv, cv;
-    sincospif(-2.0f * (float)(((16 * ti + l16) * (8 * g + e)) & 31) / 32.0f, &sv, &cv);
-    fr1[e] = (__bf16)cv;
-    fi1[e] = (__bf16)sv;
-    sincospif(-2.0f * (float)(((8 * g + e) * (16 * tj + l16)) & 31) / 32.0f, &sv, &cv);
-    fr3[e] = (__bf16)cv;
-    fi3[e] = (__bf16)sv;
+    const float2 a = w1024(32 * ((16 * ti + l16) * (8 * g + e))), b = w1024(32 * ((8 * g + e) * (16 * tj + l16)));
+    fr1[e] = (__bf16)a.x;
+    fi1[e] = (__bf16)a.y;
+    fr3[e] = (__bf16)b.x;
+    fi3[e] = (__bf16)b.y;
+    nfi3[e] = (__bf16)(-b.y);
   }
   // This lane's D items r: row i = 4 g + r (j1 = 16 ti + i), column l16 (b2 or
   // j2 = 16 tj + l16).  Twiddles w1024^(b2 j1) for step 2.
   float twr[4], twi[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int j1 = 16 * ti + 4 * g + r, b2 = 16 * tj + l16;
-    sincospif(-2.0f * (float)((j1 * b2) & (M - 1)) / (float)M, &twi[r], &twr[r]);
+    const float2 t = w1024((16 * ti + 4 * g + r) * (16 * tj + l16));
+    twr[r] = t.x;
+    twi[r] = t.y;
   }
   double pr[4] = {1.0, 1.0, 1.0, 1.0}, pi[4] = {0.0, 0.0, 0.0, 0.0};
 
-  // The first slot of the next tensor is loaded while the current one is
-  // transformed: its load latency hides behind the barriers and products.
-  float4 vn = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (nd.t0 < nd.t1) vn = load4((int64_t)tbeg[nd.t0] * M + 4 * tid);
-  for (int k = nd.t0; k < nd.t1; ++k) {
+  // Tensor k's transform.  vr holds the first slot of its sketch; once that
+  // is staged, vr is reloaded with the first slot of tensor knext, so with
+  // kAhead such registers (the loop below, unrolled) the loads of the next
+  // kAhead tensors are in flight during the barriers and products.  A register
+  // is reloaded only after its use, so no load is waited for early.
+  auto step = [&](float4 &vr, int k, int knext) {
     // stage the sketch (sum of its slots), transposed, as BF16: thread tid holds
     // points 4 tid .. 4 tid + 3 (row b1 = tid / 8, columns b2 = 4 (tid % 8) + c)
     const int a0 = tbeg[k], a1 = tend[k];
-    float4 v = vn;
-    if (k + 1 < nd.t1) vn = load4((int64_t)tbeg[k + 1] * M + 4 * tid);
+    float4 v = vr;
     for (int sl = a0 + 1; sl < a1; ++sl) {
       const float4 u = load4((int64_t)sl * M + 4 * tid);
       v.x += u.x;
@@ -98,6 +107,7 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
       yT[(c0 + 2) * kYStr + b1] = (__bf16)v.z;
       yT[(c0 + 3) * kYStr + b1] = (__bf16)v.w;
     }
+    if (knext < nd.t1) vr = load4((int64_t)tbeg[knext] * M + 4 * tid);  // kAhead tensors ahead
     __syncthreads();
     // step 1: A tile = F[16 ti .. +16][0..32) Ymat[0..32)[16 tj .. +16); the B
     // operand Ymat[8 g + e][16 tj + l16] = yT[16 tj + l16][8 g + e]
@@ -118,11 +128,8 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
     // step 3: Z tile = B[16 ti .. +16][0..32) F[0..32)[16 tj .. +16)
     const dbf16x8 xr = *reinterpret_cast<const dbf16x8 *>(bR + (16 * ti + l16) * kYStr + 8 * g);
     const dbf16x8 xi = *reinterpret_cast<const dbf16x8 *>(bI + (16 * ti + l16) * kYStr + 8 * g);
-    dbf16x8 nxi;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) nxi[e] = -xi[e];
     df32x4 zr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr, fr3, zero, 0, 0, 0);
-    zr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nxi, fi3, zr, 0, 0, 0);
+    zr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi, nfi3, zr, 0, 0, 0);
     df32x4 zi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xr, fi3, zero, 0, 0, 0);
     zi = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xi, fr3, zi, 0, 0, 0);
     // running product over the tensors, in FP64
@@ -133,6 +140,16 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
       pr[r] = nr;
       pi[r] = ni;
     }
+  };
+  constexpr int kAhead = 2;  // measured: 1, 2, 3, 4 ahead: combine 0.705, 0.658, 0.737, 0.723 ms per batched step (3 and 4 cost a wave per SIMD)
+  float4 vq[kAhead];
+#pragma unroll
+  for (int a = 0; a < kAhead; ++a)
+    vq[a] = nd.t0 + a < nd.t1 ? load4((int64_t)tbeg[nd.t0 + a] * M + 4 * tid) : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int k = nd.t0; k < nd.t1; k += kAhead) {
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a)
+      if (k + a < nd.t1) step(vq[a], k + a, k + a + kAhead);
   }
   // (1/m) Re sum over all m frequencies (each lane holds 4; the block 1024)
   double part = pr[0] + pr[1] + pr[2] + pr[3];
@@ -241,6 +258,7 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
                                                                    const int32_t *__restrict__ tend,
                                                                    const float *__restrict__ ybuf, int64_t n_slots,
                                                                    int64_t sample0, int64_t S,
+                                                                   const float2 *__restrict__ tw,
                                                                    double *__restrict__ est) {
   constexpr int M = 1024;
   __shared__ __align__(16) float yT[32 * kFStr];  // yT[b2][b1] = y[32 b1 + b2]
@@ -261,14 +279,23 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
     return v;
   };
 
-  // constant operands, as in the BF16 kernel, each as two E4M3 terms
+  // constant operands, as in the BF16 kernel (from the twiddle table), each as
+  // two E4M3 terms
+  auto w1024 = [&](int j) {
+    j &= M - 1;
+    const float2 t = tw[j & (M / 2 - 1)];
+    return j < M / 2 ? t : make_float2(-t.x, -t.y);
+  };
   dfp8x8 fr1, fi1, fr3, fi3, fr1l, fi1l, fr3l, fi3l;
   {
     float c1[8], s1[8], c3[8], s3[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      sincospif(-2.0f * (float)(((16 * ti + l16) * (8 * g + e)) & 31) / 32.0f, &s1[e], &c1[e]);
-      sincospif(-2.0f * (float)(((8 * g + e) * (16 * tj + l16)) & 31) / 32.0f, &s3[e], &c3[e]);
+      const float2 a = w1024(32 * ((16 * ti + l16) * (8 * g + e))), b = w1024(32 * ((8 * g + e) * (16 * tj + l16)));
+      c1[e] = a.x;
+      s1[e] = a.y;
+      c3[e] = b.x;
+      s3[e] = b.y;
     }
     pack_fp8_split(c1, &fr1, &fr1l);
     pack_fp8_split(s1, &fi1, &fi1l);
@@ -278,17 +305,17 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
   float twr[4], twi[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int j1 = 16 * ti + 4 * g + r, b2 = 16 * tj + l16;
-    sincospif(-2.0f * (float)((j1 * b2) & (M - 1)) / (float)M, &twi[r], &twr[r]);
+    const float2 t = w1024((16 * ti + 4 * g + r) * (16 * tj + l16));
+    twr[r] = t.x;
+    twi[r] = t.y;
   }
   double pr[4] = {1.0, 1.0, 1.0, 1.0}, pi[4] = {0.0, 0.0, 0.0, 0.0};
 
-  float4 vn = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (nd.t0 < nd.t1) vn = load4((int64_t)tbeg[nd.t0] * M + 4 * tid);
-  for (int k = nd.t0; k < nd.t1; ++k) {
+  // Tensor k's transform; the loads of the next tensors' first slots rotate
+  // through kAhead registers as in the BF16 kernel.
+  auto step = [&](float4 &vr, int k, int knext) {
     const int a0 = tbeg[k], a1 = tend[k];
-    float4 v = vn;
-    if (k + 1 < nd.t1) vn = load4((int64_t)tbeg[k + 1] * M + 4 * tid);
+    float4 v = vr;
     for (int sl = a0 + 1; sl < a1; ++sl) {
       const float4 u = load4((int64_t)sl * M + 4 * tid);
       v.x += u.x;
@@ -305,6 +332,7 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
       const float mx = wave_max(fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
       if (lane == 0) rmax[0][w] = mx;
     }
+    if (knext < nd.t1) vr = load4((int64_t)tbeg[knext] * M + 4 * tid);  // kAhead tensors ahead
     __syncthreads();
     const int s1 = fp8_scale(fmaxf(fmaxf(rmax[0][0], rmax[0][1]), fmaxf(rmax[0][2], rmax[0][3])));
     // rounding keys of this (network, sample, tensor): stage 0 the sketch, 1 and 2 B
@@ -356,6 +384,16 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
       pr[r] = nr;
       pi[r] = ni;
     }
+  };
+  constexpr int kAhead = 2;
+  float4 vq[kAhead];
+#pragma unroll
+  for (int a = 0; a < kAhead; ++a)
+    vq[a] = nd.t0 + a < nd.t1 ? load4((int64_t)tbeg[nd.t0 + a] * M + 4 * tid) : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int k = nd.t0; k < nd.t1; k += kAhead) {
+#pragma unroll
+    for (int a = 0; a < kAhead; ++a)
+      if (k + a < nd.t1) step(vq[a], k + a, k + a + kAhead);
   }
   double part = pr[0] + pr[1] + pr[2] + pr[3];
 #pragma unroll
@@ -369,12 +407,13 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
 
 int launch_m1_combine_dft32(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend,
                             const void *ybuf, int64_t n_slots, int64_t samples, int64_t sample0, int64_t S,
-                            double *est, bool fp8, hipStream_t st) {
+                            const void *twiddles, double *est, bool fp8, hipStream_t st) {
   if (n_nets == 0 || samples == 0) return TN_OK;
   if (samples > 65535) return set_error(TN_ERR_UNSUPPORTED, "combine: samples per launch");
   hipLaunchKernelGGL(fp8 ? m1_combine_dft32_fp8_kernel : m1_combine_dft32_kernel,
                      dim3((unsigned)n_nets, (unsigned)samples), dim3(256), 0, st, nets, tbeg, tend,
-                     reinterpret_cast<const float *>(ybuf), n_slots, sample0, S, est);
+                     reinterpret_cast<const float *>(ybuf), n_slots, sample0, S,
+                     reinterpret_cast<const float2 *>(twiddles), est);
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }

@@ -422,7 +422,7 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
       rc = (p->flags & (TN_FLAG_DFT_BF16 | TN_FLAG_DFT_FP8))
                ? launch_m1_combine_dft32(p->d_nets, p->n_nets, p->d_cbeg ? p->d_cbeg : p->d_tslot,
                                          p->d_cbeg ? p->d_cend : p->d_tslot + 1, p->d_ybuf,
-                                         (int64_t)p->h_slots.size(), n, c0, p->S, est,
+                                         (int64_t)p->h_slots.size(), n, c0, p->S, p->d_tw, est,
                                          (p->flags & TN_FLAG_DFT_FP8) != 0, st)
                : launch_m1_combine(p->d_nets, p->n_nets, p->d_cbeg ? p->d_cbeg : p->d_tslot,
                                    p->d_cbeg ? p->d_cend : p->d_tslot + 1, p->dtype, p->d_ybuf,
@@ -900,8 +900,8 @@ int plan_combine(tn_plan *p, hipStream_t st, double *stats, double *samples_out)
                                p->d_partial, est, st);
   else if (p->flags & (TN_FLAG_DFT_BF16 | TN_FLAG_DFT_FP8))
     rc = launch_m1_combine_dft32(p->d_nets, p->n_nets, p->d_tslot, p->d_tslot + 1, p->d_ybuf,
-                                 (int64_t)p->h_slots.size(), p->S, 0, p->S, est, (p->flags & TN_FLAG_DFT_FP8) != 0,
-                                 st);
+                                 (int64_t)p->h_slots.size(), p->S, 0, p->S, p->d_tw, est,
+                                 (p->flags & TN_FLAG_DFT_FP8) != 0, st);
   else
     rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->d_tslot + 1, p->dtype, p->d_ybuf,
                            (int64_t)p->h_slots.size(), p->S, 0, p->S, p->log2m, p->d_tw, est, st);

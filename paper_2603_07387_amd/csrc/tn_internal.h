@@ -163,7 +163,7 @@ int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, 
 // on the FP8 ones (dft.hip; FP32 sketches, m = 1024 only).
 int launch_m1_combine_dft32(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend,
                             const void *ybuf, int64_t n_slots, int64_t samples, int64_t sample0, int64_t S,
-                            double *est, bool fp8, hipStream_t st);
+                            const void *twiddles, double *est, bool fp8, hipStream_t st);
 // The two-pass combine (the m-point FFT does not fit in LDS).  pairs: n_pairs x
 // (tensor a, tensor b or -1), the tensors of each network two by two; pair0:
 // n_nets + 1 offsets into pairs.  cbuf: samples x n_pairs x m complex (A);
