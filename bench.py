@@ -13,7 +13,7 @@ Workloads (all inputs seeded and synthetic):
   batched   4096 random connected cyclic networks, 3-12 tensors, bonds
             U{2..32}, FP32 N(0,1), cyclic estimator, m = 1024, S = 16
             (1.16 GB resident); the combine's DFTs on the BF16 matrix cores
-            unless --dft fft.  Default.
+            unless --dft fft (or --persistent: that kernel has its own FFT).  Default.
   torus     4 x 4 periodic lattice of order-4 tensors, bond 16, FP32 U[0,1),
             cyclic estimator, m = 1024; a batch of B independent tori
             (B = 256: 1 GiB resident).
@@ -344,7 +344,9 @@ def main():
     f32_products = a.products == "fp32" and method == "acyclic" and dtype != "float64"
     if f32_products:
         flags |= T.TN_FLAG_MFMA_F32
-    dft = a.dft or ("bf16" if a.workload == "batched" and m == 1024 and dtype != "float64" else "fft")
+    # the persistent kernel carries its own FFT combine
+    dft = a.dft or ("bf16" if a.workload == "batched" and m == 1024 and dtype != "float64" and not a.persistent
+                    else "fft")
     dft_bf16 = dft == "bf16" and method == "cyclic"
     if dft_bf16:
         flags |= T.TN_FLAG_DFT_BF16
