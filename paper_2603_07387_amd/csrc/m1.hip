@@ -28,6 +28,8 @@ namespace {
 using namespace m1dev;
 
 
+constexpr int kStageMaxLog2M = 12;  // largest log2 m that stages the column hash words
+
 // Waves per SIMD the register allocation must allow: four (two blocks per CU)
 // for the 512-thread FP32 blocks whose loop keeps 8 loads in flight (their
 // LDS leaves room for two blocks at m = 1024); no constraint otherwise.
@@ -69,7 +71,13 @@ __global__ __launch_bounds__(NT, (kScatterWavesPerEU<T, SB, NT>)) void m1_scatte
   unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem);
   unsigned long long *s_max = reinterpret_cast<unsigned long long *>(smem + acc_end);  // [2]
   uint32_t *tabs = reinterpret_cast<uint32_t *>(smem + acc_end + 16);  // column and row tables
-  if (tid < 2) s_max[tid] = 0ull;  // the accumulators are cleared by scatter_slot
+  // Up to m = 4096 the column tables are built from hash words staged in the
+  // not yet cleared accumulators (scatter_slot clears them afterwards); above
+  // it the clear of the large accumulators is better done first (measured).
+  const bool stage = log2m <= kStageMaxLog2M;
+  if (!stage)
+    for (int i = tid; i < (int)(acc_bytes / 8); i += NT) acc[i] = 0ull;
+  if (tid < 2) s_max[tid] = 0ull;
   const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
   FixedScale fs;
   fs.lgN = max(N > 1 ? 32 - __clz(N - 1) : 0, 11);
@@ -86,7 +94,8 @@ __global__ __launch_bounds__(NT, (kScatterWavesPerEU<T, SB, NT>)) void m1_scatte
   }
   scatter_slot<T, SB, BANKS, NT, RANGED>(sl, modes, data, tables + s0 * W, W, nsb, log2m, acc, 8u * ma, signbit,
                                          tabs, s_max, fs, blockIdx.z, RANGED ? log2acc : -1,
-                                         reinterpret_cast<uint32_t *>(acc), (uint32_t)(acc_bytes / 4));
+                                         stage ? reinterpret_cast<uint32_t *>(acc) : nullptr,
+                                         stage ? (uint32_t)(acc_bytes / 4) : 0u);
   if (bound_out != nullptr && tid == 0 && blockIdx.y == 0 && blockIdx.z == 0) bound_out[blockIdx.x] = fs.bound;
   const unsigned long long *neg = acc + signbit / 8;
   const int lga = RANGED ? log2acc : log2m;
