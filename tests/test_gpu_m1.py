@@ -307,6 +307,29 @@ def test_rows_off_the_vector_grid(T, orc, monkeypatch, dtype, sb, banks):
     check_estimates(orc, plan, views, 21, dtype)
 
 
+@pytest.mark.parametrize("sb,banks", [(2, 1), (4, 2)])
+@pytest.mark.parametrize("m", [16, 1024])
+@pytest.mark.parametrize("dtype", ["float32", "bfloat16"])
+def test_table_build_paths(T, orc, monkeypatch, dtype, m, sb, banks):
+    """The scatter's table build and unaligned loops on one ring: A (600 x 3,
+    rows of 3 entries: shorter than a 16-byte vector, which then spans several
+    rows), B (111 x 37) and C (37 x 185, both rows that are no whole number of
+    vectors: a vector runs into the next row and reads the wrapped column
+    table), D (5 x 600).  At m = 1024 the column modes' hash words are staged
+    in the accumulator LDS; at m = 16 they do not fit there (B, C and D need
+    more words than the accumulators hold) and every column reads the global
+    tables.  Sketches and estimates of every sample against the oracle."""
+    monkeypatch.setenv("TN_SCATTER_SB", str(sb))
+    monkeypatch.setenv("TN_SCATTER_BANKS", str(banks))
+    rng = np.random.default_rng(13)
+    shapes = [(600, 3), (3, 37, 37), (37, 37, 5), (5, 600)]
+    net = W.Network([2, 3, 3, 2], [600, 3, 3, 37, 37, 37, 37, 5, 5, 600],
+                    [(1, 2), (3, 5), (4, 6), (7, 8), (9, 0)], [rng.standard_normal(sh) for sh in shapes])
+    plan, views = make_plan(T, [net], dtype, m, 4, 17)
+    check_sketches(orc, plan, views, 17, dtype, 0, 4)
+    check_estimates(orc, plan, views, 17, dtype)
+
+
 @pytest.mark.parametrize("dtype", ["float64", "float32", "bfloat16"])
 def test_misaligned_tensor_base(T, orc, dtype):
     """Tensors that start 1 or 3 elements past a 16-byte boundary (views at a
