@@ -75,8 +75,7 @@ __global__ __launch_bounds__(NT, (kScatterWavesPerEU<T, SB, NT>)) void m1_scatte
   // not yet cleared accumulators (scatter_slot clears them afterwards); above
   // it the clear of the large accumulators is better done first (measured).
   const bool stage = log2m <= kStageMaxLog2M;
-  if (!stage)
-    for (int i = tid; i < (int)(acc_bytes / 8); i += NT) acc[i] = 0ull;
+  if (!stage) lds_zero(acc, (uint32_t)acc_bytes, tid, NT);
   if (tid < 2) s_max[tid] = 0ull;
   const uint32_t N = (uint32_t)sl.rows * (uint32_t)sl.L;
   FixedScale fs;
@@ -99,12 +98,27 @@ __global__ __launch_bounds__(NT, (kScatterWavesPerEU<T, SB, NT>)) void m1_scatte
   if (bound_out != nullptr && tid == 0 && blockIdx.y == 0 && blockIdx.z == 0) bound_out[blockIdx.x] = fs.bound;
   const unsigned long long *neg = acc + signbit / 8;
   const int lga = RANGED ? log2acc : log2m;
-  for (int i = tid; i < (nsb << lga); i += NT) {
-    const int s = i >> lga;
-    const int b = i & (int)amask;
-    // positive bank minus negative bank
+  // (positive bank minus negative bank) 2^-scale, four buckets per thread and
+  // 16-byte accesses when a sketch has at least four
+  auto value = [&](int i) {
     const long long v = BANKS == 2 ? (long long)(acc[i] - neg[i]) : (long long)acc[i];
-    ybuf[((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + r0 + b] = (A)ldexp((double)v, -fs.scale);
+    return (A)ldexp((double)v, -fs.scale);
+  };
+  if (lga >= 2) {
+    for (int i4 = tid; i4 < (nsb << (lga - 2)); i4 += NT) {
+      const int i = 4 * i4, s = i >> lga, b = i & (int)amask;
+      const A v0 = value(i), v1 = value(i + 1), v2 = value(i + 2), v3 = value(i + 3);
+      A *dst = ybuf + ((s0 + s) * n_slots + blockIdx.x) * (int64_t)m + r0 + b;
+      if constexpr (sizeof(A) == 4) {
+        *reinterpret_cast<float4 *>(dst) = make_float4(v0, v1, v2, v3);
+      } else {
+        reinterpret_cast<double2 *>(dst)[0] = make_double2(v0, v1);
+        reinterpret_cast<double2 *>(dst)[1] = make_double2(v2, v3);
+      }
+    }
+  } else {
+    for (int i = tid; i < (nsb << lga); i += NT)
+      ybuf[((s0 + (i >> lga)) * n_slots + blockIdx.x) * (int64_t)m + r0 + (i & (int)amask)] = value(i);
   }
 }
 

@@ -63,6 +63,14 @@ __device__ __forceinline__ void load_cols<8>(const uint32_t *p, uint32_t *out) {
   load_cols<4>(p + 4, out + 4);
 }
 
+// Clear `bytes` (a multiple of 8) of 16-byte-aligned LDS with the threads of
+// a block (tid of nt): 16-byte stores, then the last 8 bytes if any.
+__device__ __forceinline__ void lds_zero(void *p, uint32_t bytes, int tid, int nt) {
+  uint4 *q = reinterpret_cast<uint4 *>(p);
+  for (uint32_t i = tid; i < bytes / 16; i += nt) q[i] = make_uint4(0u, 0u, 0u, 0u);
+  if ((bytes & 15u) && tid == 0) reinterpret_cast<unsigned long long *>(p)[bytes / 8 - 1] = 0ull;
+}
+
 // Packed bucket/sign of a contiguous run of modes for one index: the sum of
 // the modes' buckets mod m and the product of their signs.
 __device__ __forceinline__ uint32_t combine_modes(const int32_t *__restrict__ tab,
@@ -219,8 +227,7 @@ __device__ __forceinline__ void scatter_slot(const ScatterSlot &sl, const ModeDe
   }
   __syncthreads();
   if (fresh != nullptr) {  // clear the accumulators (they held the staged words)
-    unsigned long long *f8 = reinterpret_cast<unsigned long long *>(fresh);
-    for (uint32_t i = tid; i < fresh_words / 2; i += NT) f8[i] = 0ull;
+    lds_zero(fresh, fresh_words * 4u, tid, NT);
     __syncthreads();
   }
   const uint32_t amask = (mask << 3) | (BANKS == 2 ? signbit : 0u);
