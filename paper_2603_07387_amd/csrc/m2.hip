@@ -539,7 +539,13 @@ __global__ __launch_bounds__(256) void m2_gather_kernel(
   for (int64_t s = s_first; s < n_samples; s += s_step) {
     const int32_t *tab = tables ? tables + s * W : nullptr;
     if (qt >= 4 && !tab) node_coeffs(nd, (uint64_t)(sample0 + s), coef);
-    for (uint32_t i = tid; i < m; i += 256) acc[i] = 0;
+    if constexpr (sizeof(AW) == 8) {  // clear the m words: 16-byte stores (and a last 8-byte word at m = 1)
+      uint4 *a16 = reinterpret_cast<uint4 *>(acc);
+      for (uint32_t i = tid; i < m / 2; i += 256) a16[i] = make_uint4(0u, 0u, 0u, 0u);
+      if ((m & 1u) && tid == 0) acc[m - 1] = 0;
+    } else {  // 32-bit words (BF16 g): 16-byte stores measured slower here
+      for (uint32_t i = tid; i < m; i += 256) acc[i] = 0;
+    }
     // Level-one slot tables.
     if (tpre_ok) {
 #pragma unroll
