@@ -47,6 +47,25 @@ def test_estimates_against_oracle(T, orc, dtype):
     print(f"{dtype}: max |error| / scale = {worst:.3e} (bar {BAR:.3e})")
 
 
+def test_tensor_counts(T, orc):
+    """The transform loop takes the next two tensors' sketch loads in turns:
+    networks of 1 (a self-contracted matrix), 2, 6 and 7 tensors (each parity
+    of the unrolled loop, and one tensor split into two slots), every sample
+    within the bar."""
+    rng = np.random.default_rng(8)
+    nets = [W.Network([2], [40, 40], [(0, 1)], [rng.standard_normal((40, 40))]),
+            W.Network([1, 1], [300, 300], [(0, 1)], [rng.standard_normal(300), rng.standard_normal(300)]),
+            W.ring(6, 9, seed=5), W.ring(7, 11, seed=6),
+            W.Network([2, 2, 2], [300, 260, 260, 300, 300, 300], [(1, 2), (3, 4), (5, 0)],
+                      [rng.standard_normal((300, 260)), rng.standard_normal((260, 300)),
+                       rng.standard_normal((300, 300))])]
+    plan, views = make_plan(T, nets, "float32", 1024, 5, 11, flags=T.TN_FLAG_DFT_BF16)
+    _, got = run(plan)
+    for j, net in enumerate(views):
+        ref, scale = oracle_samples(orc, net, 1024, 11 + j, range(5))
+        assert np.all(np.abs(got[j] - ref) <= BAR * scale), (j, (np.abs(got[j] - ref) / scale).max())
+
+
 def test_batch_networks_and_rounding_visible(T, orc):
     """Sampled networks of the benchmark's batch: within the bar; the
     matrix-core estimates differ from the FP32 ones (BF16 rounding present);

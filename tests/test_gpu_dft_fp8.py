@@ -61,6 +61,25 @@ def test_estimates_against_oracle(T, orc, dtype):
     print(f"{dtype}: max |error| / scale = {worst:.3e} (bar {BAR:.3e})")
 
 
+def test_tensor_counts(T, orc):
+    """The loads of the next two tensors taken in turns, as in the BF16 kernel:
+    networks of 1, 2, 6, 7 and 3 tensors (one split into two slots), every
+    sample within the bar."""
+    rng = np.random.default_rng(8)
+    nets = [W.Network([2], [40, 40], [(0, 1)], [rng.standard_normal((40, 40))]),
+            W.Network([1, 1], [300, 300], [(0, 1)], [rng.standard_normal(300), rng.standard_normal(300)]),
+            W.ring(6, 9, seed=5), W.ring(7, 11, seed=6),
+            W.Network([2, 2, 2], [300, 260, 260, 300, 300, 300], [(1, 2), (3, 4), (5, 0)],
+                      [rng.standard_normal((300, 260)), rng.standard_normal((260, 300)),
+                       rng.standard_normal((300, 300))])]
+    plan, views = make_plan(T, nets, "float32", 1024, 5, 11, flags=T.TN_FLAG_DFT_FP8)
+    _, got = run(plan)
+    assert np.all(np.isfinite(got))
+    for j, net in enumerate(views):
+        ref, scale = oracle_samples(orc, net, 1024, 11 + j, range(5))
+        assert np.all(np.abs(got[j] - ref) <= BAR * scale), (j, (np.abs(got[j] - ref) / scale).max())
+
+
 def test_batch_noise_below_the_estimators_spread(T, orc):
     """64 networks of the benchmark's batch, 256 samples: FP8 against FP32 with
     the same hashes, and a few samples against the oracle."""
