@@ -32,7 +32,10 @@ CFLAGS = [
 # otherwise the compiler keeps the loop-carried accumulators of the FP64
 # products in VGPRs and copies them to and from AGPRs around every chunk, which
 # drains the matrix pipeline once per chunk.
-EXTRA = {"m2.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+EXTRA = {"m2.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+         # dft.hip: likewise, and otherwise the BF16 transform's 8 accumulator
+         # AGPRs cost it a wave per SIMD
+         "dft.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src):

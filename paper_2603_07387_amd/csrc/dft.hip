@@ -13,7 +13,8 @@
 // (j1, j2) arrangement, and the estimate only needs the sum over all
 // frequencies of the product over tensors, so no reordering is needed.
 //
-// Block: one (network, sample), four waves; wave w owns the 16 x 16 tile
+// Block: one network and kDftSamplesPerBlock of its samples in turn, four
+// waves; wave w owns the 16 x 16 tile
 // (rows 16 (w / 2), columns 16 (w % 2)) of A, of B's twiddled copy and of Z.
 // Products on v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i + 16 (k / 8) element
 // k % 8, B[k][j] in lane j + 16 (k / 8) element k % 8, D[i][j] in lane
@@ -32,12 +33,15 @@ typedef __bf16 dbf16x8 __attribute__((ext_vector_type(8)));
 typedef float df32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kYStr = 40;  // bf16 per LDS row of the staged matrices (80 bytes: rows start 16-byte aligned)
+// Samples one BF16 block transforms in turn (measured 1, 2, 4, 8: combine
+// 0.66, 0.57, 0.55, 0.57 ms per batched step).
+constexpr int kDftSamplesPerBlock = 4;
 
 __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__restrict__ nets,
                                                                const int32_t *__restrict__ tbeg,
                                                                const int32_t *__restrict__ tend,
                                                                const float *__restrict__ ybuf, int64_t n_slots,
-                                                               int64_t sample0, int64_t S,
+                                                               int64_t n_samp, int64_t sample0, int64_t S,
                                                                const float2 *__restrict__ tw,
                                                                double *__restrict__ est) {
   constexpr int M = 1024;
@@ -46,12 +50,23 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
   __shared__ __align__(16) __bf16 bI[32 * kYStr];      // imaginary part
   __shared__ double red[4];
   const NetDesc nd = nets[blockIdx.x];
-  const int64_t s = blockIdx.y;
-  const float *y = ybuf + s * n_slots * (int64_t)M;
-  auto load4 = [&](int64_t off) { return *reinterpret_cast<const float4 *>(y + off); };
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int ti = w >> 1, tj = w & 1;
   const int l16 = lane & 15, g = lane >> 4;  // operand lane (row or column, k group)
+  // The block's samples sA .. sA + ns - 1 (of this launch), one after the
+  // other: the constants below are set up once, and the tensor loop runs on
+  // across the samples, so the loads of the next sample's first tensors are
+  // in flight during the last ones of the current sample.
+  const int64_t sA = (int64_t)blockIdx.y * kDftSamplesPerBlock;
+  const int ns = (int)min((int64_t)kDftSamplesPerBlock, n_samp - sA);
+  const int p = nd.t1 - nd.t0, nsteps = ns * p;  // step g: sample g / p, tensor t0 + g % p
+  auto load4 = [&](int64_t si, int64_t off) {
+    return *reinterpret_cast<const float4 *>(ybuf + (sA + si) * n_slots * (int64_t)M + off);
+  };
+  auto load_first = [&](int gi) {  // the first slot of step gi's sketch
+    const int si = gi / p;
+    return load4(si, (int64_t)tbeg[nd.t0 + gi - si * p] * M + 4 * tid);
+  };
 
   // Constant operands, read from the plan's half table of 1024-point twiddles
   // (tw[j] = w1024^j for j < 512; w1024^(j + 512) = -tw[j]): w32^k = w1024^(32 k).
@@ -83,18 +98,22 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
   }
   double pr[4] = {1.0, 1.0, 1.0, 1.0}, pi[4] = {0.0, 0.0, 0.0, 0.0};
 
-  // Tensor k's transform.  vr holds the first slot of its sketch; once that
-  // is staged, vr is reloaded with the first slot of tensor knext, so with
-  // kAhead such registers (the loop below, unrolled) the loads of the next
-  // kAhead tensors are in flight during the barriers and products.  A register
-  // is reloaded only after its use, so no load is waited for early.
-  auto step = [&](float4 &vr, int k, int knext) {
+  constexpr int kAhead = 2;  // measured: 1, 2, 3, 4 ahead: combine 0.705, 0.658, 0.737, 0.723 ms per batched step (3 and 4 cost a wave per SIMD)
+  // Step gi's transform (sample si = gi / p, tensor k).  vr holds the first
+  // slot of its sketch; once that is staged, vr is reloaded with the first
+  // slot of step gi + kAhead, so with kAhead such registers (the loop below,
+  // unrolled) the loads of the next kAhead steps are in flight during the
+  // barriers and products.  A register is reloaded only after its use, so no
+  // load is waited for early.  After a sample's last tensor its estimate is
+  // written and the running product restarts.
+  auto step = [&](float4 &vr, int gi) {
+    const int si = gi / p, k = nd.t0 + gi - si * p;
     // stage the sketch (sum of its slots), transposed, as BF16: thread tid holds
     // points 4 tid .. 4 tid + 3 (row b1 = tid / 8, columns b2 = 4 (tid % 8) + c)
     const int a0 = tbeg[k], a1 = tend[k];
     float4 v = vr;
     for (int sl = a0 + 1; sl < a1; ++sl) {
-      const float4 u = load4((int64_t)sl * M + 4 * tid);
+      const float4 u = load4(si, (int64_t)sl * M + 4 * tid);
       v.x += u.x;
       v.y += u.y;
       v.z += u.z;
@@ -107,7 +126,7 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
       yT[(c0 + 2) * kYStr + b1] = (__bf16)v.z;
       yT[(c0 + 3) * kYStr + b1] = (__bf16)v.w;
     }
-    if (knext < nd.t1) vr = load4((int64_t)tbeg[knext] * M + 4 * tid);  // kAhead tensors ahead
+    if (gi + kAhead < nsteps) vr = load_first(gi + kAhead);
     __syncthreads();
     // step 1: A tile = F[16 ti .. +16][0..32) Ymat[0..32)[16 tj .. +16); the B
     // operand Ymat[8 g + e][16 tj + l16] = yT[16 tj + l16][8 g + e]
@@ -140,24 +159,31 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
       pr[r] = nr;
       pi[r] = ni;
     }
+    if (k == nd.t1 - 1) {  // the sample's last tensor (uniform over the block)
+      // (1/m) Re sum over all m frequencies (each lane holds 4; the block 1024).
+      // red is rewritten only after the next tensor's two barriers.
+      double part = pr[0] + pr[1] + pr[2] + pr[3];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+      if (lane == 0) red[w] = part;
+      __syncthreads();
+      if (tid == 0)
+        est[(int64_t)blockIdx.x * S + sample0 + sA + si] = (red[0] + red[1] + red[2] + red[3]) / (double)M;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pr[r] = 1.0;
+        pi[r] = 0.0;
+      }
+    }
   };
-  constexpr int kAhead = 2;  // measured: 1, 2, 3, 4 ahead: combine 0.705, 0.658, 0.737, 0.723 ms per batched step (3 and 4 cost a wave per SIMD)
   float4 vq[kAhead];
 #pragma unroll
-  for (int a = 0; a < kAhead; ++a)
-    vq[a] = nd.t0 + a < nd.t1 ? load4((int64_t)tbeg[nd.t0 + a] * M + 4 * tid) : make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int k = nd.t0; k < nd.t1; k += kAhead) {
+  for (int a = 0; a < kAhead; ++a) vq[a] = a < nsteps ? load_first(a) : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int gb = 0; gb < nsteps; gb += kAhead) {
 #pragma unroll
     for (int a = 0; a < kAhead; ++a)
-      if (k + a < nd.t1) step(vq[a], k + a, k + a + kAhead);
+      if (gb + a < nsteps) step(vq[a], gb + a);
   }
-  // (1/m) Re sum over all m frequencies (each lane holds 4; the block 1024)
-  double part = pr[0] + pr[1] + pr[2] + pr[3];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-  if (lane == 0) red[w] = part;
-  __syncthreads();
-  if (tid == 0) est[(int64_t)blockIdx.x * S + sample0 + s] = (red[0] + red[1] + red[2] + red[3]) / (double)M;
 }
 
 // ---------------------------------------------------------------------------
@@ -257,7 +283,7 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
                                                                    const int32_t *__restrict__ tbeg,
                                                                    const int32_t *__restrict__ tend,
                                                                    const float *__restrict__ ybuf, int64_t n_slots,
-                                                                   int64_t sample0, int64_t S,
+                                                                   int64_t n_samp, int64_t sample0, int64_t S,
                                                                    const float2 *__restrict__ tw,
                                                                    double *__restrict__ est) {
   constexpr int M = 1024;
@@ -410,10 +436,10 @@ int launch_m1_combine_dft32(const NetDesc *nets, int64_t n_nets, const int32_t *
                             const void *twiddles, double *est, bool fp8, hipStream_t st) {
   if (n_nets == 0 || samples == 0) return TN_OK;
   if (samples > 65535) return set_error(TN_ERR_UNSUPPORTED, "combine: samples per launch");
-  hipLaunchKernelGGL(fp8 ? m1_combine_dft32_fp8_kernel : m1_combine_dft32_kernel,
-                     dim3((unsigned)n_nets, (unsigned)samples), dim3(256), 0, st, nets, tbeg, tend,
-                     reinterpret_cast<const float *>(ybuf), n_slots, sample0, S,
-                     reinterpret_cast<const float2 *>(twiddles), est);
+  const unsigned gy = fp8 ? (unsigned)samples : (unsigned)((samples + kDftSamplesPerBlock - 1) / kDftSamplesPerBlock);
+  hipLaunchKernelGGL(fp8 ? m1_combine_dft32_fp8_kernel : m1_combine_dft32_kernel, dim3((unsigned)n_nets, gy),
+                     dim3(256), 0, st, nets, tbeg, tend, reinterpret_cast<const float *>(ybuf), n_slots, samples,
+                     sample0, S, reinterpret_cast<const float2 *>(twiddles), est);
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }
