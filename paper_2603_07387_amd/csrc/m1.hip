@@ -135,7 +135,7 @@ template <typename A, int LOG2M, bool TWL, int NTH = 256>
 __global__ __launch_bounds__(NTH) void m1_combine_kernel(
     const NetDesc *__restrict__ nets, const int32_t *__restrict__ tbeg, const int32_t *__restrict__ tend,
     const A *__restrict__ ybuf, int64_t n_slots, int64_t sample0, int64_t S,
-    const typename Cplx<A>::type *__restrict__ tw, double *__restrict__ est) {
+    const typename Cplx<A>::type *__restrict__ tw, double *__restrict__ est, double2 *__restrict__ part) {
   using A2 = typename Cplx<A>::type;
   constexpr int M = 1 << LOG2M;
   constexpr int H = M / 2 + 1;
@@ -151,6 +151,15 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
   const int64_t s = blockIdx.y;
   const A *y = ybuf + s * n_slots * (int64_t)M;
   const int tid = threadIdx.x;
+  // Tensors [kb, ke): the network's, or with part (gridDim.z blocks per
+  // network and sample) share blockIdx.z of its pairs, pairs taken from t0 on
+  // (an empty share leaves the product at 1).
+  int kb = nd.t0, ke = nd.t1;
+  if (part != nullptr) {
+    const int np = (nd.t1 - nd.t0 + 1) / 2, per = (np + (int)gridDim.z - 1) / (int)gridDim.z;
+    kb = min(nd.t1, nd.t0 + 2 * per * (int)blockIdx.z);
+    ke = min(nd.t1, kb + 2 * per);
+  }
   // Twiddles: staged in LDS after z (every butterfly pass reads them; from the
   // global table each pass would wait on a cache round trip).  The first
   // barrier below publishes them.
@@ -172,7 +181,7 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
   constexpr bool ONE_ROUND = M <= NTH * G;
   A f1[G], f2[G];
   auto first_slots = [&](int k) {
-    const bool pk = (k + 1) < nd.t1;
+    const bool pk = (k + 1) < ke;
     const int s1 = tbeg[k], s2 = pk ? tbeg[k + 1] : s1;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
@@ -182,10 +191,10 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
     }
   };
   if constexpr (ONE_ROUND)
-    if (nd.t0 < nd.t1) first_slots(nd.t0);
+    if (kb < ke) first_slots(kb);
 
-  for (int k = nd.t0; k < nd.t1; k += 2) {
-    const bool pair = (k + 1) < nd.t1;
+  for (int k = kb; k < ke; k += 2) {
+    const bool pair = (k + 1) < ke;
     // slots [a0, a1) of the first tensor of the pair, [b0, b1) of the second
     const int a0 = tbeg[k], a1 = tend[k];
     const int b0 = pair ? tbeg[k + 1] : 0, b1 = pair ? tend[k + 1] : 0;
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
     }
     __syncthreads();
     if constexpr (ONE_ROUND)
-      if (k + 2 < nd.t1) first_slots(k + 2);
+      if (k + 2 < ke) first_slots(k + 2);
     if constexpr (TWL)
       fft_lds<A, LOG2M, true, NTH>(z, t);
     else
@@ -270,14 +279,47 @@ __global__ __launch_bounds__(NTH) void m1_combine_kernel(
     __syncthreads();
   }
 
-  double part = 0.0;
+  if (part != nullptr) {  // this share's product spectrum, for m1_combine_join_kernel
+    double2 *o = part + (((int64_t)blockIdx.x * gridDim.y + s) * gridDim.z + blockIdx.z) * H;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int j = tid + NTH * c;
+      if (j < H) o[j] = make_double2(pr[c], pi[c]);
+    }
+    return;
+  }
+  double sum = 0.0;
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int j = tid + NTH * c;
-    if (j < H) part += ((j == 0 || 2 * j == M) ? 1.0 : 2.0) * pr[c];
+    if (j < H) sum += ((j == 0 || 2 * j == M) ? 1.0 : 2.0) * pr[c];
   }
-  const double tot = block_sum<NTH>(part, red);
+  const double tot = block_sum<NTH>(sum, red);
   if (tid == 0) est[(int64_t)blockIdx.x * S + sample0 + s] = tot / (double)M;
+}
+
+// The split combine's join: per (network, sample) the product over its
+// gsplit shares' spectra, in share order, then the Hermitian sum as in
+// m1_combine_kernel.
+__global__ __launch_bounds__(256) void m1_combine_join_kernel(const double2 *__restrict__ part, int gsplit,
+                                                              int64_t m, int64_t sample0, int64_t S,
+                                                              double *__restrict__ est) {
+  __shared__ double red[4];
+  const int64_t H = m / 2 + 1;
+  const double2 *q = part + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * gsplit * H;
+  double sum = 0.0;
+  for (int64_t j = threadIdx.x; j < H; j += 256) {
+    double pr = 1.0, pi = 0.0;
+    for (int g = 0; g < gsplit; ++g) {
+      const double2 v = q[(int64_t)g * H + j];
+      const double nr = pr * v.x - pi * v.y, ni = pr * v.y + pi * v.x;
+      pr = nr;
+      pi = ni;
+    }
+    sum += ((j == 0 || 2 * j == m) ? 1.0 : 2.0) * pr;
+  }
+  const double tot = block_sum<256>(sum, red);
+  if (threadIdx.x == 0) est[(int64_t)blockIdx.x * S + sample0 + blockIdx.y] = tot / (double)m;
 }
 
 // ---------------------------------------------------------------------------
@@ -601,7 +643,7 @@ int scatter_t(const M1Launch &L, hipStream_t st) {
 template <typename A, int LOG2M>
 int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend, const void *ybuf,
               int64_t n_slots, int64_t samples, int64_t sample0, int64_t S, const void *tw,
-              double *est, hipStream_t st) {
+              double *est, int32_t csplit, double *cpart, hipStream_t st) {
   using A2 = typename Cplx<A>::type;
   // z (m points, one spare element per 32: bank spread) and, when the total
   // stays within 64 KB, the m/2 twiddles (padded), else the two-level table
@@ -617,11 +659,18 @@ int combine_m(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const in
     if (lds > 65536)
       TN_HIP_CHECK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds));
-    dim3 grid((unsigned)n_nets, (unsigned)samples);
+    const bool split = csplit > 1 && cpart != nullptr;
+    dim3 grid((unsigned)n_nets, (unsigned)samples, split ? (unsigned)csplit : 1u);
+    double2 *part = split ? reinterpret_cast<double2 *>(cpart) : nullptr;
     hipLaunchKernelGGL(kern, grid, dim3(NTH), lds, st, nets, tbeg, tend,
                        reinterpret_cast<const A *>(ybuf), n_slots, sample0, S,
-                       reinterpret_cast<const A2 *>(tw), est);
+                       reinterpret_cast<const A2 *>(tw), est, part);
     TN_HIP_CHECK(hipGetLastError());
+    if (split) {
+      hipLaunchKernelGGL(m1_combine_join_kernel, dim3((unsigned)n_nets, (unsigned)samples), dim3(256), 0, st,
+                         part, (int)csplit, (int64_t)M, sample0, S, est);
+      TN_HIP_CHECK(hipGetLastError());
+    }
     return TN_OK;
   }
 }
@@ -658,9 +707,11 @@ int combine_big(int64_t n_nets, const int32_t *tslot, const int32_t *pairs, cons
 template <typename A>
 int combine_t(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend, const void *ybuf,
               int64_t n_slots, int64_t samples, int64_t sample0, int64_t S, int log2m,
-              const void *tw, double *est, hipStream_t st) {
-#define TN_COMBINE_CASE(LG) \
-  case LG: return combine_m<A, LG>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, tw, est, st);
+              const void *tw, double *est, int32_t csplit, double *cpart, hipStream_t st) {
+#define TN_COMBINE_CASE(LG)                                                                            \
+  case LG:                                                                                             \
+    return combine_m<A, LG>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, tw, est, csplit, \
+                            cpart, st);
   switch (log2m) {
     TN_COMBINE_CASE(0) TN_COMBINE_CASE(1) TN_COMBINE_CASE(2) TN_COMBINE_CASE(3)
     TN_COMBINE_CASE(4) TN_COMBINE_CASE(5) TN_COMBINE_CASE(6) TN_COMBINE_CASE(7)
@@ -687,12 +738,15 @@ int launch_m1_scatter(const M1Launch &L, hipStream_t st) {
 
 int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend, int dtype,
                       const void *ybuf, int64_t n_slots, int64_t samples, int64_t sample0,
-                      int64_t S, int log2m, const void *tw, double *est, hipStream_t st) {
+                      int64_t S, int log2m, const void *tw, double *est, int32_t csplit, double *cpart,
+                      hipStream_t st) {
   if (n_nets == 0 || samples == 0) return TN_OK;
   if (samples > 65535) return set_error(TN_ERR_UNSUPPORTED, "combine: samples per launch");
   if (dtype == TN_F64)
-    return combine_t<double>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, log2m, tw, est, st);
-  return combine_t<float>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, log2m, tw, est, st);
+    return combine_t<double>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, log2m, tw, est, csplit,
+                             cpart, st);
+  return combine_t<float>(nets, n_nets, tbeg, tend, ybuf, n_slots, samples, sample0, S, log2m, tw, est, csplit,
+                          cpart, st);
 }
 
 int launch_m1_combine_big(int64_t n_nets, const int32_t *tslot, const int32_t *pairs, const int32_t *pair0,

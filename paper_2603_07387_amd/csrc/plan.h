@@ -78,6 +78,8 @@ struct tn_plan {
   int32_t *d_pair0 = nullptr;   // [n_nets + 1]: first pair of each network
   void *d_cbuf = nullptr;       // the two-pass combine's transposed columns
   double *d_partial = nullptr;  // and its per-block row sums
+  int32_t csplit = 1;           // in-LDS combine: blocks per (network, sample), each a share of the pairs
+  double *d_csplit = nullptr;   // their partial product spectra [network][sample][block][m/2 + 1] (complex)
   int sb = 1;
   int banks = 1;            // scatter accumulator banks (autotuned: 1 or 2)
   size_t scatter_lds = 0;

@@ -19,6 +19,8 @@ namespace {
 
 constexpr int kMaxRowsPerSlot = 2048;
 constexpr size_t kWorkspaceBudget = (size_t)1 << 30;  // tables + sketches per pass
+constexpr int64_t kCombineSplitBlocks = 1024;            // combine blocks to aim for when splitting
+constexpr size_t kCombineSplitBudget = (size_t)256 << 20;  // bytes of partial spectra
 constexpr size_t kResidentBudget = (size_t)16 << 30;  // all samples' sketches and tables (TN_FLAG_RESIDENT)
 
 template <typename T>
@@ -320,6 +322,25 @@ int m1_layout(tn_plan *p, const std::vector<NetCheck> *chkp) {
     p->d_cbuf = cb;
     if ((rc = dev_alloc(&p->d_partial, (size_t)chunk * (size_t)p->n_nets * kBigPartials)) != TN_OK) return rc;
   }
+  // In-LDS combine with too few (network, sample) blocks to fill the GPU (one
+  // network with many tensors, as the ladder): each (network, sample) takes
+  // csplit blocks, each the product over a share of the tensor pairs, and a
+  // join kernel multiplies the partial spectra.
+  p->csplit = 1;
+  if (!p->two_pass && !p->fused && !(p->flags & (TN_FLAG_DFT_BF16 | TN_FLAG_DFT_FP8))) {
+    int64_t max_pairs = 0;
+    for (const NetDesc &nd : p->h_nets) max_pairs = std::max<int64_t>(max_pairs, (nd.t1 - nd.t0 + 1) / 2);
+    const int64_t blocks = (int64_t)p->n_nets * p->chunk_alloc;
+    if (blocks > 0 && blocks < kCombineSplitBlocks / 2 && max_pairs >= 2) {
+      const size_t H = (size_t)p->m / 2 + 1;
+      int64_t gs = std::min<int64_t>({(kCombineSplitBlocks + blocks - 1) / blocks, max_pairs, 64});
+      while (gs > 1 && (size_t)blocks * (size_t)gs * H * 16 > kCombineSplitBudget) --gs;
+      if (gs > 1) {
+        if ((rc = dev_alloc(&p->d_csplit, (size_t)blocks * (size_t)gs * H * 2)) != TN_OK) return rc;
+        p->csplit = (int32_t)gs;
+      }
+    }
+  }
   if (p->m >= 2) {
     unsigned char *tw = nullptr;
     if ((rc = dev_alloc(&tw, (size_t)(p->m / 2) * 2 * as)) != TN_OK) return rc;
@@ -426,7 +447,8 @@ int m1_run(tn_plan *p, hipStream_t st, double *est) {
                                          (p->flags & TN_FLAG_DFT_FP8) != 0, st)
                : launch_m1_combine(p->d_nets, p->n_nets, p->d_cbeg ? p->d_cbeg : p->d_tslot,
                                    p->d_cbeg ? p->d_cend : p->d_tslot + 1, p->dtype, p->d_ybuf,
-                                   (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, est, st);
+                                   (int64_t)p->h_slots.size(), n, c0, p->S, p->log2m, p->d_tw, est, p->csplit,
+                                   p->d_csplit, st);
     if (rc != TN_OK) return rc;
     if ((rc = prof_end(p, st, TN_KERNEL_COMBINE, ev)) != TN_OK) return rc;
   }
@@ -824,7 +846,7 @@ void plan_release(tn_plan *p) {
   void *ptrs[] = {p->d_streams, p->d_tables, p->d_injected, p->d_data,    p->d_modes,
                   p->d_slots,   p->d_tslot,  p->d_nets,     p->d_tw,      p->d_ybuf,
                   p->d_est,     p->d_items,  p->d_counter,  p->d_tensor_lgn, p->d_cbuf, p->d_partial,
-                  p->d_pairs,   p->d_pair0,  p->d_slot_bound};
+                  p->d_pairs,   p->d_pair0,  p->d_slot_bound, p->d_csplit};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
   p->d_streams = nullptr;
@@ -838,6 +860,7 @@ void plan_release(tn_plan *p) {
   p->d_partial = nullptr;
   p->d_pairs = p->d_pair0 = nullptr;
   p->d_slot_bound = nullptr;
+  p->d_csplit = nullptr;
   p->d_est = nullptr;
   p->d_items = nullptr;
   p->d_counter = p->d_tensor_lgn = nullptr;
@@ -904,7 +927,8 @@ int plan_combine(tn_plan *p, hipStream_t st, double *stats, double *samples_out)
                                  (p->flags & TN_FLAG_DFT_FP8) != 0, st);
   else
     rc = launch_m1_combine(p->d_nets, p->n_nets, p->d_tslot, p->d_tslot + 1, p->dtype, p->d_ybuf,
-                           (int64_t)p->h_slots.size(), p->S, 0, p->S, p->log2m, p->d_tw, est, st);
+                           (int64_t)p->h_slots.size(), p->S, 0, p->S, p->log2m, p->d_tw, est, p->csplit,
+                           p->d_csplit, st);
   if (rc != TN_OK) return rc;
   return launch_sample_stats(est, p->n_nets, p->S, stats, st);
 }

@@ -158,7 +158,7 @@ int launch_m1_scatter(const M1Launch &L, hipStream_t st);
 int launch_m1_combine(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend,
                       int dtype, const void *ybuf, int64_t n_slots, int64_t samples,
                       int64_t sample0, int64_t S, int log2m, const void *twiddles,
-                      double *est, hipStream_t st);
+                      double *est, int32_t csplit, double *cpart, hipStream_t st);
 // The combine with its 1024-point DFTs on the BF16 matrix cores, or with fp8
 // on the FP8 ones (dft.hip; FP32 sketches, m = 1024 only).
 int launch_m1_combine_dft32(const NetDesc *nets, int64_t n_nets, const int32_t *tbeg, const int32_t *tend,
