@@ -13,7 +13,7 @@
 // (j1, j2) arrangement, and the estimate only needs the sum over all
 // frequencies of the product over tensors, so no reordering is needed.
 //
-// Block: one network and kDftSamplesPerBlock of its samples in turn, four
+// Block: one network and spb of its samples in turn (see the launcher), four
 // waves; wave w owns the 16 x 16 tile
 // (rows 16 (w / 2), columns 16 (w % 2)) of A, of B's twiddled copy and of Z.
 // Products on v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i + 16 (k / 8) element
@@ -33,15 +33,18 @@ typedef __bf16 dbf16x8 __attribute__((ext_vector_type(8)));
 typedef float df32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kYStr = 40;  // bf16 per LDS row of the staged matrices (80 bytes: rows start 16-byte aligned)
-// Samples one BF16 block transforms in turn (measured 1, 2, 4, 8: combine
-// 0.66, 0.57, 0.55, 0.57 ms per batched step).
+// Samples one BF16 block transforms in turn when the launch has enough
+// (network, sample) pairs to fill the GPU anyway (measured on the batch, 1, 2,
+// 4, 8: combine 0.66, 0.57, 0.55, 0.57 ms per step); one otherwise, so that a
+// plan of few networks keeps its blocks.
 constexpr int kDftSamplesPerBlock = 4;
+constexpr int64_t kDftSplitPairs = 16384;  // (network, sample) pairs from which blocks take kDftSamplesPerBlock
 
 __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__restrict__ nets,
                                                                const int32_t *__restrict__ tbeg,
                                                                const int32_t *__restrict__ tend,
                                                                const float *__restrict__ ybuf, int64_t n_slots,
-                                                               int64_t n_samp, int64_t sample0, int64_t S,
+                                                               int64_t n_samp, int spb, int64_t sample0, int64_t S,
                                                                const float2 *__restrict__ tw,
                                                                double *__restrict__ est) {
   constexpr int M = 1024;
@@ -57,8 +60,8 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_kernel(const NetDesc *__
   // other: the constants below are set up once, and the tensor loop runs on
   // across the samples, so the loads of the next sample's first tensors are
   // in flight during the last ones of the current sample.
-  const int64_t sA = (int64_t)blockIdx.y * kDftSamplesPerBlock;
-  const int ns = (int)min((int64_t)kDftSamplesPerBlock, n_samp - sA);
+  const int64_t sA = (int64_t)blockIdx.y * spb;
+  const int ns = (int)min((int64_t)spb, n_samp - sA);
   const int p = nd.t1 - nd.t0, nsteps = ns * p;  // step g: sample g / p, tensor t0 + g % p
   auto load4 = [&](int64_t si, int64_t off) {
     return *reinterpret_cast<const float4 *>(ybuf + (sA + si) * n_slots * (int64_t)M + off);
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(256) void m1_combine_dft32_fp8_kernel(const NetDesc
                                                                    const int32_t *__restrict__ tbeg,
                                                                    const int32_t *__restrict__ tend,
                                                                    const float *__restrict__ ybuf, int64_t n_slots,
-                                                                   int64_t n_samp, int64_t sample0, int64_t S,
+                                                                   int64_t n_samp, int spb, int64_t sample0, int64_t S,
                                                                    const float2 *__restrict__ tw,
                                                                    double *__restrict__ est) {
   constexpr int M = 1024;
@@ -436,10 +439,11 @@ int launch_m1_combine_dft32(const NetDesc *nets, int64_t n_nets, const int32_t *
                             const void *twiddles, double *est, bool fp8, hipStream_t st) {
   if (n_nets == 0 || samples == 0) return TN_OK;
   if (samples > 65535) return set_error(TN_ERR_UNSUPPORTED, "combine: samples per launch");
-  const unsigned gy = fp8 ? (unsigned)samples : (unsigned)((samples + kDftSamplesPerBlock - 1) / kDftSamplesPerBlock);
+  const int spb = !fp8 && n_nets * samples >= kDftSplitPairs ? kDftSamplesPerBlock : 1;
+  const unsigned gy = (unsigned)((samples + spb - 1) / spb);
   hipLaunchKernelGGL(fp8 ? m1_combine_dft32_fp8_kernel : m1_combine_dft32_kernel, dim3((unsigned)n_nets, gy),
                      dim3(256), 0, st, nets, tbeg, tend, reinterpret_cast<const float *>(ybuf), n_slots, samples,
-                     sample0, S, reinterpret_cast<const float2 *>(twiddles), est);
+                     spb, sample0, S, reinterpret_cast<const float2 *>(twiddles), est);
   TN_HIP_CHECK(hipGetLastError());
   return TN_OK;
 }

@@ -21,6 +21,7 @@ constexpr int kMaxRowsPerSlot = 2048;
 constexpr size_t kWorkspaceBudget = (size_t)1 << 30;  // tables + sketches per pass
 constexpr int64_t kCombineSplitBlocks = 1024;            // combine blocks to aim for when splitting
 constexpr size_t kCombineSplitBudget = (size_t)256 << 20;  // bytes of partial spectra
+constexpr int64_t kCombineSplitWork = 65536;               // least (pairs x m) of a network worth splitting
 constexpr size_t kResidentBudget = (size_t)16 << 30;  // all samples' sketches and tables (TN_FLAG_RESIDENT)
 
 template <typename T>
@@ -331,7 +332,9 @@ int m1_layout(tn_plan *p, const std::vector<NetCheck> *chkp) {
     int64_t max_pairs = 0;
     for (const NetDesc &nd : p->h_nets) max_pairs = std::max<int64_t>(max_pairs, (nd.t1 - nd.t0 + 1) / 2);
     const int64_t blocks = (int64_t)p->n_nets * p->chunk_alloc;
-    if (blocks > 0 && blocks < kCombineSplitBlocks / 2 && max_pairs >= 2) {
+    // (only for long products: the join is one more launch, which small
+    // networks, launch-bound, do not repay)
+    if (blocks > 0 && blocks < kCombineSplitBlocks / 2 && max_pairs >= 2 && max_pairs * p->m >= kCombineSplitWork) {
       const size_t H = (size_t)p->m / 2 + 1;
       int64_t gs = std::min<int64_t>({(kCombineSplitBlocks + blocks - 1) / blocks, max_pairs, 64});
       while (gs > 1 && (size_t)blocks * (size_t)gs * H * 16 > kCombineSplitBudget) --gs;

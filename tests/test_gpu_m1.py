@@ -374,14 +374,15 @@ def test_bounds_follow_the_data(T, orc):
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
 def test_combine_split_over_pairs(T, orc, dtype):
-    """Few (network, sample) blocks: the in-LDS combine splits each network's
-    tensor pairs over several blocks and joins their product spectra.  A ring
-    of 13 tensors (an odd one out), a triangle (whose later shares are empty)
-    and a single self-contracted matrix at S = 4, against the oracle."""
+    """Few (network, sample) blocks and a long product (pairs x m >= 65536):
+    the in-LDS combine splits each network's tensor pairs over several blocks
+    and joins their product spectra.  A ring of 33 tensors (an odd one out), a
+    triangle (whose later shares are empty) and a single self-contracted
+    matrix at m = 4096, S = 4, against the oracle."""
     rng = np.random.default_rng(21)
-    nets = [W.ring(13, 7, seed=3), W.triangle(12, seed=4),
+    nets = [W.ring(33, 5, seed=3), W.triangle(12, seed=4),
             W.Network([2], [9, 9], [(0, 1)], [rng.standard_normal((9, 9))])]
-    plan, views = make_plan(T, nets, dtype, 256, 4, 5)
+    plan, views = make_plan(T, nets, dtype, 4096, 4, 5)
     check_estimates(orc, plan, views, 5, dtype)
 
 
