@@ -456,6 +456,24 @@ def test_graph_replay(T, orc):
         del junk
 
 
+def test_graph_replay_split_combine(T, orc):
+    """A captured estimate whose combine is split over the pairs (one long
+    ring, few blocks): three replays with eager work between them, each
+    bitwise the eager run's estimates, and those against the oracle."""
+    import torch
+    nets = [W.ring(33, 5, seed=7)]
+    plan_g, views = make_plan(T, nets, "float64", 4096, 3, 9, flags=T.TN_FLAG_GRAPH)
+    plan_e, _ = make_plan(T, nets, "float64", 4096, 3, 9)
+    _, ref = run(plan_e)
+    for rep in range(3):
+        junk = torch.randn(1000, device="cuda").sum()      # eager work between replays
+        _, got = run(plan_g)
+        assert np.array_equal(got, ref)
+        del junk
+    want, scale = oracle_samples(orc, views[0], 4096, 9, range(3))
+    assert np.all(np.abs(ref[0] - want) <= TAU["float64"] * scale)
+
+
 def test_graph_replay_after_data_change(T, orc):
     """A replayed graph takes the slot bounds afresh: the tensors scaled in
     place by 2^12 between replays (same pointers), every sample of both
