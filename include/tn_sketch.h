@@ -214,7 +214,12 @@ typedef struct tn_plan tn_plan;
  *                  sample per pass; when the m-point FFT does not fit in LDS,
  *                  from 16384 with TN_F64 data and 32768 otherwise, the combine
  *                  runs in two passes through a device workspace of
- *                  tensors x m complex values per sample),
+ *                  tensors x m complex values per sample; when a launch has
+ *                  under 512 (network, sample) pairs and a network's pairs of
+ *                  tensors times m reach 65536, each (network, sample) is
+ *                  combined by several blocks over shares of its pairs, with
+ *                  a workspace of their m/2 + 1 complex products, at most
+ *                  256 MB),
  *                  2 <= m <= 8192 for TN_ACYCLIC.
  *   samples      : S >= 1 independent sketch samples per network (S <= 0
  *                  only with m <= 0: chosen too); sample r
@@ -339,7 +344,9 @@ const char *tn_last_error(void);
  * of the cyclic sketching pass (1 or 2; 0 for TN_ACYCLIC), 11 = 1 when the
  * persistent kernel runs the plan (TN_FLAG_PERSISTENT), 12 = estimates per
  * sample (n_nets; a partial plan: its output entries), 13 = free modes of a
- * partial plan (0 otherwise).  Keys 8 and 10 may
+ * partial plan (0 otherwise), 14 = blocks per (network, sample) of the
+ * cyclic in-LDS combine (1, or more when a plan of few networks has a long
+ * product: see tn_sketch_plan; 0 for TN_ACYCLIC).  Keys 8 and 10 may
  * change after the first estimate of a TN_FLAG_AUTOTUNE plan.
  * Returns the value, or a negative code.
  */

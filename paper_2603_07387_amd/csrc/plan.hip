@@ -885,6 +885,7 @@ int64_t plan_query(const tn_plan *p, int key) {
     case 11: return p->fused ? 1 : 0;
     case 12: return p->partial ? p->n_out : p->n_nets;
     case 13: return p->partial ? p->n_free : 0;
+    case 14: return p->m2 ? 0 : p->csplit;
     default: return set_error(TN_ERR_ARG, "unknown query key %d", key);
   }
 }

@@ -383,7 +383,10 @@ def test_combine_split_over_pairs(T, orc, dtype):
     nets = [W.ring(33, 5, seed=3), W.triangle(12, seed=4),
             W.Network([2], [9, 9], [(0, 1)], [rng.standard_normal((9, 9))])]
     plan, views = make_plan(T, nets, dtype, 4096, 4, 5)
+    assert plan.query(14) > 1          # blocks per (network, sample)
     check_estimates(orc, plan, views, 5, dtype)
+    short, _ = make_plan(T, nets[1:], dtype, 4096, 4, 5)   # 2 pairs x 4096 < 65536: not split
+    assert short.query(14) == 1
 
 
 @pytest.mark.parametrize("m,S", [(1, 3), (2, 5), (4, 7), (32, 1), (64, 17)])
